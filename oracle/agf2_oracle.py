@@ -1,0 +1,567 @@
+"""Plain FP64 CPU oracle for AGF2(1,0) (Backhouse, Santana-Bonilla & Booth,
+"Scalable and predictive spectra of correlated molecules with moment truncated
+iterated perturbation theory", arXiv 2106.03508).
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product library may import, call or
+link this file; only the tests, the smoke check and the benchmark's CPU
+baseline leg use it. It shares no code with the GPU path: numpy and LAPACK
+(through numpy.linalg) only, float64 throughout, no blocking or fusion beyond
+what each definition states.
+
+Notation follows the paper: N physical orbitals (p, q, x, y), a Green's
+function written as poles (energies lam, physical amplitudes u[N, npole]),
+occupied poles i, j (below the chemical potential) and virtual poles a, b.
+The DF tensor L[Q, p, q] factorises (pq|rs) = sum_Q L[Q,p,q] L[Q,r,s].
+
+Readings of passages the paper leaves open are marked "Reading:" where used.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+# ----------------------------------------------------------------------------
+# Integrals and the Fock matrix
+# ----------------------------------------------------------------------------
+
+def eri_4index(L):
+    """(pq|rs) = sum_Q L[Q,p,q] L[Q,r,s] as a dense [N,N,N,N] array
+    (density fitting, the factorisation the cost analysis assumes)."""
+    return np.einsum("Qpq,Qrs->pqrs", L, L, optimize=True)
+
+
+def coulomb_exchange(L, D):
+    """J_pq = sum_rs (pq|rs) D_rs and K_pq = sum_rs (ps|rq) D_rs, DF form."""
+    rho = np.einsum("Qrs,rs->Q", L, D)
+    J = np.einsum("Q,Qpq->pq", rho, L)
+    K = np.einsum("Qps,sr,Qrq->pq", L, D, L, optimize=True)
+    return J, K
+
+
+def fock_matrix(h, L, D):
+    """Generalised Fock matrix of the paper's Fock-matrix equation (section
+    reviewing the method): F = h + sum_rs [(pq|rs) - 1/2 (ps|rq)] D_rs, with D
+    the spin-summed one-body density matrix."""
+    J, K = coulomb_exchange(L, D)
+    return h + J - 0.5 * K
+
+
+def synthetic_hcore(eps, L, nocc):
+    """Reading: a synthetic system has no one-electron Hamiltonian of its own.
+    Choose h so that the closed-shell determinant D0 = 2 * diag(1_occ) is a
+    self-consistent mean-field solution with orbital energies eps:
+    F[D0] = diag(eps) exactly (Fock-matrix equation solved for h)."""
+    N = eps.shape[0]
+    D0 = np.zeros((N, N))
+    D0[np.arange(nocc), np.arange(nocc)] = 2.0
+    J, K = coulomb_exchange(L, D0)
+    return np.diag(eps) - J + 0.5 * K
+
+
+def reference_density(nmo, nocc):
+    D0 = np.zeros((nmo, nmo))
+    D0[np.arange(nocc), np.arange(nocc)] = 2.0
+    return D0
+
+
+# ----------------------------------------------------------------------------
+# Self-energy moments (zeroth- and first-moment equations; second-order
+# self-energy equation for the lesser/greater split)
+# ----------------------------------------------------------------------------
+
+def pole_basis_df(L, u_pole, nocc_pole):
+    """DF tensors in the pole basis: Lxo[Q,x,i] = sum_r L[Q,x,r] u[r,i],
+    Lxv[Q,x,a] likewise, Lov[Q,i,a] = sum_xr u[x,i] L[Q,x,r] u[r,a]."""
+    uo = u_pole[:, :nocc_pole]
+    uv = u_pole[:, nocc_pole:]
+    Lxo = np.einsum("Qxr,ri->Qxi", L, uo, optimize=True)
+    Lxv = np.einsum("Qxr,ra->Qxa", L, uv, optimize=True)
+    Lov = np.einsum("xi,Qxa->Qia", uo, Lxv, optimize=True)
+    return Lxo, Lxv, Lov
+
+
+def se_moments(L, e_pole, u_pole, nocc_pole):
+    """Zeroth and first moments of the lesser and greater second-order
+    self-energy, built from the Green's function poles (e_pole, u_pole).
+
+    Lesser (first term of the second-order self-energy equation; the
+    zeroth/first moment equations):
+        U0<_pq = sum_{ija} (pi|ja) [2 (qi|ja) - (qj|ia)]
+        U1<_pq = same summand times (e_i + e_j - e_a)
+    Greater (second term; "analogous expressions" after the Cholesky step):
+        U0>_pq = sum_{abi} (pa|bi) [2 (qa|bi) - (qb|ai)]
+        U1>_pq = same summand times (e_a + e_b - e_i)
+    Reading: at self-consistent iterations i, j, a, b run over the occupied
+    and virtual poles of the dressed Green's function, with the integrals
+    transformed by the poles' physical amplitudes u and weighted by the pole
+    energies.
+
+    Evaluated literally, one summed pole at a time, with the integrals taken
+    from the DF factorisation. Returns (U0<, U1<, U0>, U1>).
+    """
+    N = u_pole.shape[0]
+    Q = L.shape[0]
+    eo = e_pole[:nocc_pole]
+    ev = e_pole[nocc_pole:]
+    o, v = eo.shape[0], ev.shape[0]
+    Lxo, Lxv, Lov = pole_basis_df(L, u_pole, nocc_pole)
+    Lxo_m = np.ascontiguousarray(Lxo.reshape(Q, N * o))       # [Q, (x,j)]
+    Lxv_m = np.ascontiguousarray(Lxv.reshape(Q, N * v))       # [Q, (x,b)]
+    Lov_m = np.ascontiguousarray(Lov.reshape(Q, o * v))       # [Q, (j,a)]
+    Lvo_m = np.ascontiguousarray(Lov.transpose(0, 2, 1).reshape(Q, v * o))  # [Q, (b,i)]
+    m0o = np.zeros((N, N)); m1o = np.zeros((N, N))
+    m0v = np.zeros((N, N)); m1v = np.zeros((N, N))
+    for i in range(o):
+        xija = (Lxo[:, :, i].T @ Lov_m).reshape(N, o, v)               # (xi|ja)
+        xjia = (Lxo_m.T @ Lov[:, i, :]).reshape(N, o, v)              # (xj|ia)
+        w = eo[i] + eo[:, None] - ev[None, :]
+        a = xija.reshape(N, -1)
+        t = (2.0 * xija - xjia).reshape(N, -1)
+        m0o += a @ t.T
+        m1o += (a * w.reshape(1, -1)) @ t.T
+    for a_ in range(v):
+        xabi = (Lxv[:, :, a_].T @ Lvo_m).reshape(N, v, o)             # (xa|bi)
+        xbai = (Lxv_m.T @ Lov[:, :, a_]).reshape(N, v, o)             # (xb|ai)
+        w = ev[a_] + ev[:, None] - eo[None, :]
+        a = xabi.reshape(N, -1)
+        t = (2.0 * xabi - xbai).reshape(N, -1)
+        m0v += a @ t.T
+        m1v += (a * w.reshape(1, -1)) @ t.T
+    return m0o, m1o, m0v, m1v
+
+
+def se_moments_4index(eri, e_pole, u_pole, nocc_pole):
+    """The same moments from explicit four-index integrals, transformed to
+    the pole basis and summed with plain loops over the summed poles.
+    Independent of the DF slab route; for tiny systems only."""
+    uo = u_pole[:, :nocc_pole]
+    uv = u_pole[:, nocc_pole:]
+    eo = e_pole[:nocc_pole]
+    ev = e_pole[nocc_pole:]
+    # (p i | j a) and (p a | b i), p physical
+    ovo = np.einsum("pqrs,qi,rj,sa->pija", eri, uo, uo, uv, optimize=True)
+    vvo = np.einsum("pqrs,qa,rb,si->pabi", eri, uv, uv, uo, optimize=True)
+    N = eri.shape[0]
+    o, v = eo.shape[0], ev.shape[0]
+    m0o = np.zeros((N, N)); m1o = np.zeros((N, N))
+    m0v = np.zeros((N, N)); m1v = np.zeros((N, N))
+    for i in range(o):
+        for j in range(o):
+            for a in range(v):
+                left = ovo[:, i, j, a]
+                right = 2.0 * ovo[:, i, j, a] - ovo[:, j, i, a]
+                outer = np.outer(left, right)
+                m0o += outer
+                m1o += outer * (eo[i] + eo[j] - ev[a])
+    for a in range(v):
+        for b in range(v):
+            for i in range(o):
+                left = vvo[:, a, b, i]
+                right = 2.0 * vvo[:, a, b, i] - vvo[:, b, a, i]
+                outer = np.outer(left, right)
+                m0v += outer
+                m1v += outer * (ev[a] + ev[b] - eo[i])
+    return m0o, m1o, m0v, m1v
+
+
+def uncompressed_self_energy(L, e_pole, u_pole, nocc_pole):
+    """Explicit auxiliary (pole) form of the second-order self-energy,
+    Sigma_pq(w) = sum_k v_pk v_qk / (w - E_k) (auxiliary self-energy
+    equation), for tiny systems. The exchange-weighted numerator
+    X^{ij} (2X^{ij} - X^{ji})^T, summed over an (i, j) pair and its mirror,
+    is a sum of squares: with P = X^{ij} + X^{ji}, M = X^{ij} - X^{ji} it is
+    1/2 P P^T + 3/2 M M^T, and X^{ii} X^{ii T} on the diagonal, where
+    X^{ij}[x, a] = (xi|ja). Each column is one auxiliary with energy
+    e_i + e_j - e_a (lesser) or e_a + e_b - e_i (greater).
+
+    Returns (E<, v<, E>, v>) with v of shape [N, naux]."""
+    Lxo, Lxv, Lov = pole_basis_df(L, u_pole, nocc_pole)
+    eo = e_pole[:nocc_pole]
+    ev = e_pole[nocc_pole:]
+
+    def build(Lx, Lpc, ep, ec, sign):
+        # X[p][q][x, c] = sum_Q Lx[Q,x,p] Lpc(q)[Q,c]
+        n = ep.shape[0]
+        E, V = [], []
+        for p in range(n):
+            for q in range(p, n):
+                Xpq = Lx[:, :, p].T @ Lpc(q)   # [x, c]
+                if p == q:
+                    for c in range(ec.shape[0]):
+                        V.append(Xpq[:, c]); E.append(ep[p] + ep[p] - ec[c])
+                    continue
+                Xqp = Lx[:, :, q].T @ Lpc(p)
+                for c in range(ec.shape[0]):
+                    V.append(np.sqrt(0.5) * (Xpq[:, c] + Xqp[:, c]))
+                    E.append(ep[p] + ep[q] - ec[c])
+                    V.append(np.sqrt(1.5) * (Xpq[:, c] - Xqp[:, c]))
+                    E.append(ep[p] + ep[q] - ec[c])
+        return np.array(E), np.array(V).T
+
+    Eo, Vo = build(Lxo, lambda j: Lov[:, j, :], eo, ev, +1)
+    Ev, Vv = build(Lxv, lambda b: Lov[:, :, b], ev, eo, -1)
+    return Eo, Vo, Ev, Vv
+
+
+def mp2_energy_bruteforce(eri, eps, nocc):
+    """Closed-shell MP2 correlation energy with plain loops:
+    sum_{ijab} (ia|jb)[2(ia|jb) - (ib|ja)] / (e_i + e_j - e_a - e_b)."""
+    N = eps.shape[0]
+    e = 0.0
+    for i in range(nocc):
+        for j in range(nocc):
+            for a in range(nocc, N):
+                for b in range(nocc, N):
+                    iajb = eri[i, a, j, b]
+                    ibja = eri[i, b, j, a]
+                    e += iajb * (2.0 * iajb - ibja) / (eps[i] + eps[j] - eps[a] - eps[b])
+    return e
+
+
+# ----------------------------------------------------------------------------
+# Compression: one block-Lanczos step through a Cholesky factor
+# ----------------------------------------------------------------------------
+
+class NotPositiveDefinite(RuntimeError):
+    pass
+
+
+def compress(m0, m1, tol=0.0):
+    """Auxiliaries conserving the zeroth and first moments (block Lanczos,
+    single step, via Cholesky; compression section).
+
+    Reading: the paper writes T T^dagger = U0 and M = (T^-1)^dagger U1 T^-1,
+    which agree only for the upper factor. Any square root S with
+    S S^T = U0 gives the same self-energy; take the lower Cholesky factor,
+    M = S^-1 U1 S^-T, diagonalise M = W diag(e) W^T and couple the
+    auxiliaries through v = S W, so v v^T = U0 and v diag(e) v^T = U1.
+
+    tol == 0: strict Cholesky, NotPositiveDefinite on failure.
+    tol > 0: square root from the eigendecomposition of U0 keeping
+    eigenvalues above tol * max eigenvalue (fewer auxiliaries when U0 is
+    singular).
+    Returns (e[naux], v[N, naux])."""
+    if tol == 0.0:
+        try:
+            S = np.linalg.cholesky(m0)
+        except np.linalg.LinAlgError as exc:
+            raise NotPositiveDefinite(str(exc)) from exc
+        Sinv = np.linalg.inv(S)
+        M = Sinv @ m1 @ Sinv.T
+    else:
+        s, Z = np.linalg.eigh(m0)
+        keep = s > tol * s.max()
+        if not np.any(keep):
+            raise NotPositiveDefinite("zeroth moment has no positive eigenvalue")
+        S = Z[:, keep] * np.sqrt(s[keep])
+        Spinv = (Z[:, keep] / np.sqrt(s[keep])).T
+        M = Spinv @ m1 @ Spinv.T
+    M = 0.5 * (M + M.T)
+    e, W = np.linalg.eigh(M)
+    return e, S @ W
+
+
+def self_energy_at(w, e_aux, v_aux):
+    """Sigma(w) = sum_k v_k v_k^T / (w - e_k) (auxiliary self-energy eq.)."""
+    return (v_aux / (w - e_aux)) @ v_aux.T
+
+
+# ----------------------------------------------------------------------------
+# Fock loop: extended Fock matrix, aufbau, chemical potential, density
+# ----------------------------------------------------------------------------
+
+def extended_hamiltonian(F, e_aux, v_aux):
+    """[[F, v], [v^T, diag(e)]] (compressed extended Hamiltonian equation)."""
+    N = F.shape[0]
+    n = e_aux.shape[0]
+    H = np.zeros((N + n, N + n))
+    H[:N, :N] = F
+    H[:N, N:] = v_aux
+    H[N:, :N] = v_aux.T
+    H[N:, N:] = np.diag(e_aux)
+    return H
+
+
+def aufbau(lam, u, nelec):
+    """Reading: fill the poles in ascending energy, two electrons times each
+    pole's physical weight |u_l|^2; the occupied count n* minimises
+    |c_n - nelec| with c_n = 2 sum_{l<n} |u_l|^2 (ties -> smaller n). The
+    chemical potential sits midway between the last occupied and first
+    virtual pole. Returns (n*, c_{n*}, mu)."""
+    w = np.sum(u * u, axis=0)
+    c = 2.0 * np.concatenate([[0.0], np.cumsum(w)])
+    n = int(np.argmin(np.abs(c - nelec)))
+    npole = lam.shape[0]
+    if 0 < n < npole:
+        mu = 0.5 * (lam[n - 1] + lam[n])
+    elif n == 0:
+        mu = lam[0] - 1.0
+    else:
+        mu = lam[-1] + 1.0
+    return n, c[n], mu
+
+
+def _solve(F, e_aux, v_aux, shift, nelec):
+    H = extended_hamiltonian(F, e_aux + shift, v_aux)
+    lam, phi = np.linalg.eigh(H)
+    N = F.shape[0]
+    u = phi[:N]
+    n, cnt, mu = aufbau(lam, u, nelec)
+    return lam, u, n, cnt, mu
+
+
+def fit_shift(F, e_aux, v_aux, nelec, shift0=0.0, bracket=2.0, tol=1e-10,
+              step0=0.01, max_iter=100):
+    """Reading of the chemical-potential condition (electron number kept
+    exact in a non-idempotent density): shift every auxiliary energy by a
+    common Delta until the aufbau count equals nelec.
+
+    For a fixed number n of occupied poles, c_n(Delta) is non-decreasing in
+    Delta (the sum of the n lowest eigenvalues is concave in Delta and its
+    derivative is n - c_n/2), so the root of g(Delta) = c_n(Delta) - nelec is
+    bracketed by stepping away from shift0 (step0, doubling, never beyond
+    shift0 +- bracket) and then refined by regula falsi with the Illinois
+    modification, stopping when |g| < tol. If the aufbau picks another n at
+    the root, repeat with that n.
+    Returns (shift, n_eig) with n_eig the number of eigensolves used."""
+    n_eig = 1
+    lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift0, nelec)
+    shift = shift0
+    for _ in range(8):
+        g0 = cnt - nelec
+        if abs(g0) < tol:
+            return shift, n_eig
+
+        def g(d):
+            lam_, u_, nn_, cnt_, mu_ = _solve(F, e_aux, v_aux, d, nelec)
+            return 2.0 * np.sum(u_[:, :n] ** 2) - nelec
+
+        # bracket: g is non-decreasing, so move up when g < 0
+        direction = 1.0 if g0 < 0 else -1.0
+        a, ga = shift, g0
+        step = step0
+        b, gb = a, ga
+        while True:
+            b = shift + direction * min(step, bracket)
+            gb = g(b); n_eig += 1
+            if gb == 0.0 or (gb > 0) != (ga > 0) or step >= bracket:
+                break
+            a, ga = b, gb
+            step *= 2.0
+        if (gb > 0) == (ga > 0) and gb != 0.0:
+            shift = b          # no sign change inside the allowed bracket
+        else:
+            # Illinois regula falsi on [a, b]
+            side = 0
+            x = b
+            for _ in range(max_iter):
+                if gb == 0.0:
+                    x = b
+                    break
+                x = b - gb * (b - a) / (gb - ga)
+                gx = g(x); n_eig += 1
+                if abs(gx) < tol:
+                    break
+                if (gx > 0) == (gb > 0):
+                    b, gb = x, gx
+                    if side == -1:
+                        ga *= 0.5
+                    side = -1
+                else:
+                    a, ga = b, gb
+                    b, gb = x, gx
+                    side = +1
+            shift = x
+        lam, u, n_new, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
+        n_eig += 1
+        if n_new == n:
+            return shift, n_eig
+        n = n_new
+    return shift, n_eig
+
+
+def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
+              max_cycle=50, bracket=2.0, shift0=0.0, diis_space=6):
+    """Density relaxation with the chemical potential held at the right
+    electron number (relaxation passage after the self-consistency
+    discussion), on the compressed extended Hamiltonian.
+
+    Each cycle: Delta fitted at the current F; eigendecomposition of
+    [[F, v], [v^T, diag(e + Delta)]]; aufbau; D = 2 sum_{l<n*} u_l u_l^T;
+    stop when the RMS change of D is below tol_rdm1, else the next F is
+    F[D], DIIS-extrapolated with the fixed-point residual F[D] - F as error.
+    The returned F is the one diagonalised last, so the returned poles are
+    exact eigenpairs of the returned extended Hamiltonian.
+    Returns a dict."""
+    F = fock_matrix(h, L, D)
+    shift = shift0
+    n_eig = 0
+    converged = False
+    diis = DIIS(diis_space) if diis_space else None
+    N = F.shape[0]
+    for cycle in range(1, max_cycle + 1):
+        shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift,
+                              bracket=bracket, tol=tol_nelec)
+        n_eig += ne
+        lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
+        n_eig += 1
+        uo = u[:, :n]
+        D_new = 2.0 * uo @ uo.T
+        err = np.sqrt(np.mean((D_new - D) ** 2))
+        D = D_new
+        if err < tol_rdm1:
+            converged = True
+            break
+        F_new = fock_matrix(h, L, D)
+        if diis is not None:
+            F_new = diis.update(F_new, err=F_new - F).reshape(N, N)
+        F = F_new
+    return dict(e_pole=lam, u_pole=u, nocc_pole=n, mu=mu, shift=shift,
+                rdm1=D, fock=F, n_cycle=cycle, n_eig=n_eig, converged=converged,
+                nelec=cnt)
+
+
+# ----------------------------------------------------------------------------
+# Energy and observables
+# ----------------------------------------------------------------------------
+
+def energy_gf(h, F, D, e_pole, u_pole, nocc_pole, e_occ_aux, v_occ_aux,
+              e_vir_aux, v_vir_aux):
+    """Galitskii-Migdal energy of a Green's function and its self-energy.
+
+    Reading (the paper mentions static energetics but prints no formula):
+    for poles (lam_l, u_l) that are eigenpairs of [[F, v], [v^T, diag(e)]],
+    GM gives E = 1/2 Tr[(h + F) D] + sum_{l occ} sum_k (u_l.v_k)^2/(lam_l - e_k).
+    Because sum over all l of (u_l.v_k)^2/(lam_l - e_k) vanishes for every
+    auxiliary k (the physical-auxiliary block of the eigenvector completeness
+    relation), the lesser-auxiliary part of that sum equals a virtual-pole
+    sum, so
+      E_2b = sum_{l occ} sum_{k>} (u_l.v_k)^2/(lam_l - e_k)
+           + sum_{l vir} sum_{k<} (u_l.v_k)^2/(e_k - lam_l),
+    which has no near-zero denominators. Returns (E_1b, E_2b)."""
+    e1b = 0.5 * np.sum((h + F) * D)
+    uo = u_pole[:, :nocc_pole]
+    uv = u_pole[:, nocc_pole:]
+    lo = e_pole[:nocc_pole]
+    lv = e_pole[nocc_pole:]
+    c_ov = (uo.T @ v_vir_aux) ** 2                        # [l occ, k >]
+    e2b = np.sum(c_ov / (lo[:, None] - e_vir_aux[None, :]))
+    c_vo = (uv.T @ v_occ_aux) ** 2                        # [l vir, k <]
+    e2b += np.sum(c_vo / (e_occ_aux[None, :] - lv[:, None]))
+    return e1b, e2b
+
+
+def energy_gf_onesided_all(h, F, D, e_pole, u_pole, nocc_pole, e_aux, v_aux):
+    """GM two-body term in its direct form, occupied poles against every
+    auxiliary: sum_{l occ} sum_k (u_l.v_k)^2/(lam_l - e_k)."""
+    uo = u_pole[:, :nocc_pole]
+    lo = e_pole[:nocc_pole]
+    c = (uo.T @ v_aux) ** 2
+    return np.sum(c / (lo[:, None] - e_aux[None, :]))
+
+
+def ip_ea(e_pole, u_pole, nocc_pole):
+    """IP = -(energy of the highest occupied pole), EA = energy of the
+    lowest virtual pole, with their quasiparticle weights |u|^2."""
+    w = np.sum(u_pole * u_pole, axis=0)
+    return (-e_pole[nocc_pole - 1], e_pole[nocc_pole],
+            w[nocc_pole - 1], w[nocc_pole])
+
+
+# ----------------------------------------------------------------------------
+# Outer self-consistency
+# ----------------------------------------------------------------------------
+
+class DIIS:
+    """Pulay (DIIS) extrapolation over the last `space` iterates. The error
+    vector of an iterate is either given, or taken as the change since the
+    previous iterate."""
+
+    def __init__(self, space=8):
+        self.space = space
+        self.xs = []
+        self.es = []
+        self.prev = None
+
+    def update(self, x, err=None):
+        x = np.asarray(x, dtype=np.float64).ravel()
+        if err is None:
+            if self.prev is None:
+                self.prev = x.copy()
+                return x
+            e = x - self.prev
+            self.prev = x.copy()
+        else:
+            e = np.asarray(err, dtype=np.float64).ravel()
+        self.xs.append(x.copy()); self.es.append(e.copy())
+        if len(self.xs) > self.space:
+            self.xs.pop(0); self.es.pop(0)
+        n = len(self.xs)
+        if n < 2:
+            return x
+        B = np.zeros((n + 1, n + 1))
+        for a in range(n):
+            for b in range(n):
+                B[a, b] = self.es[a] @ self.es[b]
+        B[n, :n] = B[:n, n] = -1.0
+        rhs = np.zeros(n + 1); rhs[n] = -1.0
+        try:
+            c = np.linalg.solve(B, rhs)[:n]
+        except np.linalg.LinAlgError:
+            return x
+        out = np.zeros_like(x)
+        for ci, xi in zip(c, self.xs):
+            out += ci * xi
+        return out
+
+
+def run_agf2(h, L, eps, nocc, max_iter=20, conv_tol=1e-8, conv_tol_ipea=1e-7,
+             diis_space=8, fock_opts=None, compress_tol=0.0, verbose=False):
+    """AGF2(1,0) to self-consistency (the method as reviewed in the paper):
+    start from the mean-field poles; each iteration builds the four moments
+    from the current poles, extrapolates them (DIIS), compresses the lesser
+    and greater parts to N auxiliaries each, relaxes the density in the Fock
+    loop, and evaluates the energy and IP/EA. Converged when the energy
+    changes by less than conv_tol and IP/EA by less than conv_tol_ipea."""
+    fock_opts = dict(fock_opts or {})
+    N = eps.shape[0]
+    nelec = 2 * nocc
+    e_pole = eps.copy()
+    u_pole = np.eye(N)
+    nocc_pole = nocc
+    D = reference_density(N, nocc)
+    diis = DIIS(diis_space) if diis_space else None
+    hist = []
+    prev = None
+    converged = False
+    for it in range(max_iter + 1):
+        m = se_moments(L, e_pole, u_pole, nocc_pole)
+        if diis is not None:
+            flat = diis.update(np.concatenate([x.ravel() for x in m]))
+            m = tuple(flat[k * N * N:(k + 1) * N * N].reshape(N, N) for k in range(4))
+        m = tuple(0.5 * (x + x.T) for x in m)
+        eo, vo = compress(m[0], m[1], tol=compress_tol)
+        ev, vv = compress(m[2], m[3], tol=compress_tol)
+        e_aux = np.concatenate([eo, ev])
+        v_aux = np.hstack([vo, vv])
+        fl = fock_loop(h, L, nelec, e_aux, v_aux, D, **fock_opts)
+        e_pole, u_pole, nocc_pole, D = fl["e_pole"], fl["u_pole"], fl["nocc_pole"], fl["rdm1"]
+        shift = fl["shift"]
+        e1b, e2b = energy_gf(h, fl["fock"], D, e_pole, u_pole, nocc_pole,
+                             eo + shift, vo, ev + shift, vv)
+        ip, ea, wip, wea = ip_ea(e_pole, u_pole, nocc_pole)
+        rec = dict(iter=it, e1b=e1b, e2b=e2b, etot=e1b + e2b, ip=ip, ea=ea,
+                   wip=wip, wea=wea, nocc_pole=nocc_pole, npole=e_pole.shape[0],
+                   mu=fl["mu"], shift=shift, fock_cycles=fl["n_cycle"],
+                   fock_eig=fl["n_eig"], fock_converged=fl["converged"])
+        hist.append(rec)
+        if verbose:
+            print(rec)
+        if prev is not None:
+            if (abs(rec["etot"] - prev["etot"]) < conv_tol
+                    and max(abs(ip - prev["ip"]), abs(ea - prev["ea"])) < conv_tol_ipea):
+                converged = True
+                break
+        prev = rec
+    return dict(history=hist, converged=converged, e_pole=e_pole, u_pole=u_pole,
+                nocc_pole=nocc_pole, rdm1=D, e_aux=e_aux, v_aux=v_aux)
