@@ -1,0 +1,225 @@
+/*
+ * agf2.h -- C ABI of the MI355X (gfx950) AGF2(1,0) library.
+ *
+ * AGF2(1,0): auxiliary second-order Green's function theory with the
+ * self-energy compressed each iteration so that its zeroth and first spectral
+ * moments are conserved (Backhouse, Santana-Bonilla & Booth, arXiv
+ * 2106.03508). The library computes, on one GPU:
+ *   - the self-energy moments (the O(N^5) step),
+ *   - their compression to auxiliaries by one block-Lanczos step,
+ *   - the Fock loop (extended Fock matrix, chemical potential, density),
+ *   - the Galitskii-Migdal energy,
+ *   - the outer self-consistent loop built from the calls above.
+ *
+ * Conventions (all entry points):
+ *   - Arrays are row-major float64 unless stated otherwise.
+ *   - Pointers documented "device" must point to device memory on the
+ *     handle's device; the caller owns them, the library never frees them.
+ *     Pointers documented "host" are host memory.
+ *   - Calls are ordered on the handle's stream. A call that returns host
+ *     scalars synchronises that stream before returning.
+ *   - Every call returns an agf2_status; AGF2_OK is 0 and errors are
+ *     negative. agf2_last_error() gives a message for the last failure on the
+ *     handle. No C++ exception crosses this boundary.
+ *   - A handle must not be used by two threads at once. It owns a device
+ *     workspace that grows on demand and is freed by agf2_destroy().
+ *
+ * Notation: nphys = N physical orbitals; naux = Q density-fitting functions
+ * with (pq|rs) = sum_Q L[Q][p][q] L[Q][r][s]; a Green's function is a set of
+ * npole poles with energies e_pole (ascending) and physical amplitudes
+ * u_pole[N][npole]; the first nocc_pole poles are occupied.
+ */
+#ifndef AGF2_H
+#define AGF2_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct agf2_handle_s* agf2_handle_t;
+
+typedef enum {
+  AGF2_OK = 0,
+  AGF2_ERR_ARG = -1,          /* invalid argument (size, pointer, value)      */
+  AGF2_ERR_HIP = -2,          /* a HIP / rocBLAS / rocSOLVER call failed      */
+  AGF2_ERR_NOMEM = -3,        /* device workspace allocation failed           */
+  AGF2_ERR_NOT_PD = -4,       /* zeroth moment not positive definite          */
+  AGF2_ERR_NO_CONVERGE = -5,  /* an iteration hit its cycle limit             */
+  AGF2_ERR_NELEC = -6         /* electron number cannot be reached            */
+} agf2_status;
+
+typedef enum {
+  AGF2_FP64 = 0,        /* float64 operands, FP64 MFMA, float64 accumulation  */
+  AGF2_SPLIT_BF16 = 1   /* float32-stored operands split into bf16 hi/lo, three
+                           bf16 MFMA products, float32 accumulation over
+                           bounded chunks, float64 compensated accumulation    */
+} agf2_precision;
+
+/* Create a handle on HIP device `device`. All work is ordered on
+ * `hip_stream`, a hipStream_t owned by the caller; NULL is the device's
+ * default (null) stream. */
+agf2_status agf2_create(agf2_handle_t* handle, int device, void* hip_stream);
+
+/* Release the handle and its workspace (the stream is left alone). */
+agf2_status agf2_destroy(agf2_handle_t handle);
+
+/* Message describing the last error on the handle (static storage owned by
+ * the handle; valid until the next call on it). NULL handle -> generic text. */
+const char* agf2_last_error(agf2_handle_t handle);
+
+/* Block the host until all work queued on the handle's stream is done. */
+agf2_status agf2_synchronize(agf2_handle_t handle);
+
+/*
+ * Self-energy moments: the zeroth- and first-moment equations of the
+ * compression section, for the lesser part (first term of the second-order
+ * self-energy equation) and the greater part (its second term):
+ *   m0_occ[p][q] = sum_{i,j occ; a vir} (pi|ja) [2(qi|ja) - (qj|ia)]
+ *   m1_occ[p][q] = same summand times (e_i + e_j - e_a)
+ *   m0_vir[p][q] = sum_{a,b vir; i occ} (pa|bi) [2(qa|bi) - (qb|ai)]
+ *   m1_vir[p][q] = same summand times (e_a + e_b - e_i)
+ * with (pi|ja) = sum_{Q,r,s,t} L[Q][p][r] u[r][i] L[Q][s][t] u[s][j] u[t][a].
+ *
+ *   prec       AGF2_FP64 or AGF2_SPLIT_BF16 (see agf2_precision).
+ *   nphys      N >= 1.      naux  Q >= 1.
+ *   Lpq        device, [naux][nphys][nphys], symmetric in (p,q).
+ *   npole      number of Green's function poles (>= 2).
+ *   nocc_pole  occupied poles, 1 <= nocc_pole < npole.
+ *   e_pole     device, [npole] pole energies.
+ *   u_pole     device, [nphys][npole] physical amplitudes.
+ *   m0_occ, m1_occ, m0_vir, m1_vir   device, [nphys][nphys] outputs,
+ *              exactly symmetric.
+ * Errors: AGF2_ERR_ARG for bad sizes or NULL pointers, AGF2_ERR_NOMEM when
+ * the workspace cannot grow, AGF2_ERR_HIP for a failed launch.
+ */
+agf2_status agf2_build_moments(agf2_handle_t handle, agf2_precision prec,
+                               int nphys, int naux, const double* Lpq,
+                               int npole, int nocc_pole, const double* e_pole,
+                               const double* u_pole, double* m0_occ,
+                               double* m1_occ, double* m0_vir, double* m1_vir);
+
+/*
+ * Generalised Fock matrix (Fock-matrix equation of the method review):
+ *   fock = hcore + alpha * sum_rs [(pq|rs) - 1/2 (ps|rq)] rdm1[r][s]
+ * rdm1 is the spin-summed density matrix. alpha = 1 is the Fock matrix;
+ * other values scale the two-electron part (alpha = -1 with
+ * hcore = diag(eps) gives the one-electron Hamiltonian that makes a
+ * determinant self-consistent with orbital energies eps).
+ *   Lpq   device [naux][nphys][nphys]; hcore, rdm1 device [nphys][nphys]
+ *   fock  device [nphys][nphys] output (may not alias the inputs).
+ */
+agf2_status agf2_fock_build(agf2_handle_t handle, int nphys, int naux,
+                            const double* Lpq, const double* hcore,
+                            const double* rdm1, double alpha, double* fock);
+
+/*
+ * Compression of one part (lesser or greater) of the self-energy: one step
+ * of block Lanczos through a Cholesky factor (compression section). With
+ * S S^T = m0 (lower Cholesky factor), M = S^-1 m1 S^-T = W diag(e) W^T,
+ * the auxiliaries are e_aux = e and v_aux = S W, so
+ * v_aux v_aux^T = m0 and v_aux diag(e_aux) v_aux^T = m1.
+ *   m0, m1     device [nphys][nphys], symmetric (m0 positive definite).
+ *   tol        0: strict Cholesky, AGF2_ERR_NOT_PD if it fails.
+ *              > 0: square root from the eigendecomposition of m0, keeping
+ *              eigenvalues > tol * max eigenvalue (fewer auxiliaries).
+ *   naux_out   host, number of auxiliaries written (nphys for tol = 0).
+ *   e_aux      device [nphys] output (first naux_out entries valid).
+ *   v_aux      device [nphys][nphys] output, column k couples auxiliary k
+ *              (columns >= naux_out are zero).
+ */
+agf2_status agf2_compress(agf2_handle_t handle, int nphys, const double* m0,
+                          const double* m1, double tol, int* naux_out,
+                          double* e_aux, double* v_aux);
+
+/* Options of the Fock loop. */
+typedef struct {
+  double tol_rdm1;    /* stop when the RMS change of the density is below   */
+  double tol_nelec;   /* |electron count - nelec| target of the shift fit   */
+  double bracket;     /* largest shift step tried, Ha                        */
+  double step0;       /* first shift step of the bracket search, Ha          */
+  int max_cycle;      /* density cycles                                      */
+  int diis_space;     /* DIIS vectors on the Fock matrix (0 = off)           */
+} agf2_fock_opts;
+
+/* Fill opts with the defaults: tol_rdm1 1e-8, tol_nelec 1e-10, bracket 2,
+ * step0 0.01, max_cycle 50, diis_space 6. */
+void agf2_fock_opts_default(agf2_fock_opts* opts);
+
+/*
+ * Fock loop: relax the density with the self-energy held fixed while a
+ * chemical potential keeps the electron number (relaxation passage after
+ * the self-consistency discussion; compressed extended Hamiltonian).
+ * Each cycle fits a common shift Delta of all auxiliary energies so that
+ * the aufbau count 2 * sum_{l<n} |u_l|^2 equals nelec, diagonalises
+ *   [[F, v_se], [v_se^T, diag(e_se + Delta)]],
+ * rebuilds rdm1 = 2 sum_{l<n} u_l u_l^T and F = F[rdm1] (DIIS on F), until
+ * the RMS change of rdm1 is below tol_rdm1.
+ *   hcore      device [nphys][nphys]; Lpq device [naux][nphys][nphys]
+ *   nelec      electrons (even, 0 < nelec < 2 * (nphys + naux_se))
+ *   naux_se    auxiliaries; v_se device [nphys][naux_se] (row stride
+ *              naux_se); e_se device [naux_se], in: auxiliary energies,
+ *              out: the same energies plus the fitted shift
+ *   rdm1       device [nphys][nphys], in: starting density, out: final
+ *   fock       device [nphys][nphys] out: the Fock matrix of the last
+ *              diagonalisation
+ *   e_pole     device [nphys + naux_se] out: pole energies, ascending
+ *   u_pole     device [nphys][nphys + naux_se] out: physical amplitudes
+ *   nocc_pole, mu, shift, n_cycle   host outputs
+ *   opts       host, NULL for defaults
+ * Returns AGF2_ERR_NO_CONVERGE (outputs hold the last cycle) when the cycle
+ * limit is hit, AGF2_ERR_NELEC when nelec is out of range.
+ */
+agf2_status agf2_fock_loop(agf2_handle_t handle, int nphys, int naux,
+                           const double* Lpq, const double* hcore, int nelec,
+                           int naux_se, double* e_se, const double* v_se,
+                           double* rdm1, double* fock, double* e_pole,
+                           double* u_pole, int* nocc_pole, double* mu,
+                           double* shift, int* n_cycle,
+                           const agf2_fock_opts* opts);
+
+/*
+ * Galitskii-Migdal energy of a Green's function whose poles are eigenpairs of
+ * the extended Hamiltonian built from `fock` and the auxiliaries:
+ *   e_1b = 1/2 Tr[(hcore + fock) rdm1]
+ *   e_2b = sum_{l occ} sum_{k in vir aux} (u_l . v_k)^2 / (e_l - e_k)
+ *        + sum_{l vir} sum_{k in occ aux} (u_l . v_k)^2 / (e_k - e_l)
+ * (the two-body term in a form without near-zero denominators; equal to the
+ * direct occupied-pole sum over all auxiliaries for exact eigenpairs).
+ *   e_pole [npole], u_pole [nphys][npole] device; first nocc_pole occupied.
+ *   e_se_occ [naux_occ], v_se_occ [nphys][naux_occ] device (lesser part),
+ *   e_se_vir [naux_vir], v_se_vir [nphys][naux_vir] device (greater part),
+ *   with the Fock loop's shift already applied to the energies.
+ *   e_1b, e_2b host outputs.
+ */
+agf2_status agf2_energy_gf(agf2_handle_t handle, int nphys,
+                           const double* hcore, const double* fock,
+                           const double* rdm1, int npole, int nocc_pole,
+                           const double* e_pole, const double* u_pole,
+                           int naux_occ, const double* e_se_occ,
+                           const double* v_se_occ, int naux_vir,
+                           const double* e_se_vir, const double* v_se_vir,
+                           double* e_1b, double* e_2b);
+
+/*
+ * Kernel timing (tracing aid, not part of the method). When enabled, the
+ * library records hipEvents on its stream around every launch of each
+ * kernel class (e.g. "moments.slab", "moments.syrk", "fock.syevd") together
+ * with the launch's algorithmic flop and HBM byte counts.
+ * agf2_profile_enable(h, 1) clears the totals and starts recording;
+ * agf2_profile_enable(h, 0) stops. agf2_profile_count() synchronises the
+ * stream, folds pending events into the totals and returns the number of
+ * classes (or a negative status); agf2_profile_get() reads class `idx`
+ * (name valid until the next profile call): launches, total milliseconds,
+ * total algorithmic flops and bytes.
+ */
+agf2_status agf2_profile_enable(agf2_handle_t handle, int enable);
+int agf2_profile_count(agf2_handle_t handle);
+agf2_status agf2_profile_get(agf2_handle_t handle, int idx, const char** name,
+                             long* launches, double* ms, double* flops,
+                             double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AGF2_H */

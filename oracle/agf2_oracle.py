@@ -80,7 +80,7 @@ def pole_basis_df(L, u_pole, nocc_pole):
     return Lxo, Lxv, Lov
 
 
-def se_moments(L, e_pole, u_pole, nocc_pole):
+def se_moments(L, e_pole, u_pole, nocc_pole, occ_sel=None, vir_sel=None):
     """Zeroth and first moments of the lesser and greater second-order
     self-energy, built from the Green's function poles (e_pole, u_pole).
 
@@ -97,7 +97,10 @@ def se_moments(L, e_pole, u_pole, nocc_pole):
     energies.
 
     Evaluated literally, one summed pole at a time, with the integrals taken
-    from the DF factorisation. Returns (U0<, U1<, U0>, U1>).
+    from the DF factorisation. occ_sel / vir_sel restrict the outermost sum
+    (over i for the lesser part, over a for the greater part) to a subset of
+    poles; the full moments are the sums of these partial contributions.
+    Returns (U0<, U1<, U0>, U1>).
     """
     N = u_pole.shape[0]
     Q = L.shape[0]
@@ -111,7 +114,7 @@ def se_moments(L, e_pole, u_pole, nocc_pole):
     Lvo_m = np.ascontiguousarray(Lov.transpose(0, 2, 1).reshape(Q, v * o))  # [Q, (b,i)]
     m0o = np.zeros((N, N)); m1o = np.zeros((N, N))
     m0v = np.zeros((N, N)); m1v = np.zeros((N, N))
-    for i in range(o):
+    for i in (range(o) if occ_sel is None else occ_sel):
         xija = (Lxo[:, :, i].T @ Lov_m).reshape(N, o, v)               # (xi|ja)
         xjia = (Lxo_m.T @ Lov[:, i, :]).reshape(N, o, v)              # (xj|ia)
         w = eo[i] + eo[:, None] - ev[None, :]
@@ -119,7 +122,7 @@ def se_moments(L, e_pole, u_pole, nocc_pole):
         t = (2.0 * xija - xjia).reshape(N, -1)
         m0o += a @ t.T
         m1o += (a * w.reshape(1, -1)) @ t.T
-    for a_ in range(v):
+    for a_ in (range(v) if vir_sel is None else vir_sel):
         xabi = (Lxv[:, :, a_].T @ Lvo_m).reshape(N, v, o)             # (xa|bi)
         xbai = (Lxv_m.T @ Lov[:, :, a_]).reshape(N, v, o)             # (xb|ai)
         w = ev[a_] + ev[:, None] - eo[None, :]

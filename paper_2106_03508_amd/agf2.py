@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libagf2.so (C ABI declared in include/agf2.h).
+
+Argument marshalling only: every function checks that its tensors are
+float64, contiguous and on the handle's GPU, allocates outputs with torch
+(device memory), and passes raw pointers to the library. No arithmetic of the
+method happens here. The library must be built (``python -m
+paper_2106_03508_amd.build`` or ``__graft_entry__.build()``); importing the
+binding without it, or calling it without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libagf2.so")
+
+AGF2_FP64 = 0
+AGF2_SPLIT_BF16 = 1
+PRECISIONS = {"fp64": AGF2_FP64, "split_bf16": AGF2_SPLIT_BF16}
+
+STATUS = {0: "AGF2_OK", -1: "AGF2_ERR_ARG", -2: "AGF2_ERR_HIP", -3: "AGF2_ERR_NOMEM",
+          -4: "AGF2_ERR_NOT_PD", -5: "AGF2_ERR_NO_CONVERGE", -6: "AGF2_ERR_NELEC"}
+
+# exported entry points (name -> (restype, argtypes))
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_IP = ctypes.POINTER(ctypes.c_int)
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+class FockOpts(ctypes.Structure):
+    _fields_ = [("tol_rdm1", _D), ("tol_nelec", _D), ("bracket", _D), ("step0", _D),
+                ("max_cycle", _I), ("diis_space", _I)]
+
+
+SIGNATURES = {
+    "agf2_create": (_I, [ctypes.POINTER(_P), _I, _P]),
+    "agf2_destroy": (_I, [_P]),
+    "agf2_last_error": (ctypes.c_char_p, [_P]),
+    "agf2_synchronize": (_I, [_P]),
+    "agf2_build_moments": (_I, [_P, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P, _P]),
+    "agf2_fock_build": (_I, [_P, _I, _I, _P, _P, _P, _D, _P]),
+    "agf2_compress": (_I, [_P, _I, _P, _P, _D, _IP, _P, _P]),
+    "agf2_fock_opts_default": (None, [ctypes.POINTER(FockOpts)]),
+    "agf2_fock_loop": (_I, [_P, _I, _I, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, _IP, _DP,
+                            _DP, _IP, ctypes.POINTER(FockOpts)]),
+    "agf2_energy_gf": (_I, [_P, _I, _P, _P, _P, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P,
+                            _DP, _DP]),
+    "agf2_profile_enable": (_I, [_P, _I]),
+    "agf2_profile_count": (_I, [_P]),
+    "agf2_profile_get": (_I, [_P, _I, ctypes.POINTER(ctypes.c_char_p),
+                              ctypes.POINTER(ctypes.c_long), _DP, _DP, _DP]),
+}
+
+_lib = None
+
+
+class Agf2Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libagf2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t: torch.Tensor, name: str, dev: torch.device) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if t.device != dev:
+        raise ValueError(f"{name} must be on {dev}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+class Handle:
+    """An agf2 handle bound to a GPU and to torch's current stream there."""
+
+    def __init__(self, device: int = 0, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("agf2 needs a ROCm GPU; none is visible")
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = _P()
+        self._check(self.lib.agf2_create(ctypes.byref(h), device, _P(stream.cuda_stream)), None)
+        self.h = h
+
+    def _check(self, status, h=None):
+        if status != 0:
+            msg = self.lib.agf2_last_error(h if h is not None else self.h)
+            raise Agf2Error(status, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.agf2_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def synchronize(self):
+        self._check(self.lib.agf2_synchronize(self.h))
+
+    def empty(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+
+def agf2_create(device: int = 0, stream=None) -> Handle:
+    return Handle(device, stream)
+
+
+def agf2_build_moments(h: Handle, L, e_pole, u_pole, nocc_pole: int, prec="fp64", out=None):
+    """Moments (m0_occ, m1_occ, m0_vir, m1_vir) of the poles (e_pole, u_pole)."""
+    naux, nphys, _ = L.shape
+    npole = e_pole.shape[0]
+    if out is None:
+        out = tuple(h.empty(nphys, nphys) for _ in range(4))
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    d = h.device
+    h._check(h.lib.agf2_build_moments(
+        h.h, p, nphys, naux, _ptr(L, "L", d), npole, nocc_pole, _ptr(e_pole, "e_pole", d),
+        _ptr(u_pole, "u_pole", d), *[_ptr(m, "moment", d) for m in out]))
+    return out
+
+
+def agf2_fock_build(h: Handle, L, hcore, rdm1, alpha=1.0, out=None):
+    naux, nphys, _ = L.shape
+    out = h.empty(nphys, nphys) if out is None else out
+    d = h.device
+    h._check(h.lib.agf2_fock_build(h.h, nphys, naux, _ptr(L, "L", d), _ptr(hcore, "hcore", d),
+                                   _ptr(rdm1, "rdm1", d), float(alpha), _ptr(out, "fock", d)))
+    return out
+
+
+def agf2_compress(h: Handle, m0, m1, tol=0.0):
+    """Returns (naux, e_aux[nphys], v_aux[nphys, nphys]); columns >= naux are zero."""
+    nphys = m0.shape[0]
+    e = h.empty(nphys)
+    v = h.empty(nphys, nphys)
+    n = ctypes.c_int(0)
+    d = h.device
+    h._check(h.lib.agf2_compress(h.h, nphys, _ptr(m0, "m0", d), _ptr(m1, "m1", d), float(tol),
+                                 ctypes.byref(n), _ptr(e, "e_aux", d), _ptr(v, "v_aux", d)))
+    return n.value, e, v
+
+
+def fock_opts(**kw) -> FockOpts:
+    o = FockOpts()
+    load_library().agf2_fock_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def agf2_fock_loop(h: Handle, L, hcore, nelec: int, e_se, v_se, rdm1, opts: FockOpts = None,
+                   raise_on_no_converge=True):
+    """Fock loop. e_se (shifted in place) and rdm1 (updated in place) are
+    modified. Returns a dict with fock, e_pole, u_pole, nocc_pole, mu, shift,
+    n_cycle, converged."""
+    naux, nphys, _ = L.shape
+    naux_se = e_se.shape[0]
+    npole = nphys + naux_se
+    fock = h.empty(nphys, nphys)
+    e_pole = h.empty(npole)
+    u_pole = h.empty(nphys, npole)
+    nocc = ctypes.c_int(0)
+    mu = ctypes.c_double(0.0)
+    shift = ctypes.c_double(0.0)
+    ncyc = ctypes.c_int(0)
+    d = h.device
+    st = h.lib.agf2_fock_loop(
+        h.h, nphys, naux, _ptr(L, "L", d), _ptr(hcore, "hcore", d), int(nelec), naux_se,
+        _ptr(e_se, "e_se", d), _ptr(v_se, "v_se", d), _ptr(rdm1, "rdm1", d),
+        _ptr(fock, "fock", d), _ptr(e_pole, "e_pole", d), _ptr(u_pole, "u_pole", d),
+        ctypes.byref(nocc), ctypes.byref(mu), ctypes.byref(shift), ctypes.byref(ncyc),
+        ctypes.byref(opts) if opts is not None else None)
+    converged = st == 0
+    if st != 0 and (st != -5 or raise_on_no_converge):
+        h._check(st)
+    return dict(fock=fock, e_pole=e_pole, u_pole=u_pole, nocc_pole=nocc.value, mu=mu.value,
+                shift=shift.value, n_cycle=ncyc.value, converged=converged, rdm1=rdm1)
+
+
+def agf2_energy_gf(h: Handle, hcore, fock, rdm1, e_pole, u_pole, nocc_pole, e_se_occ, v_se_occ,
+                   e_se_vir, v_se_vir):
+    """(e_1b, e_2b). v_se_* are [nphys, naux_*] contiguous."""
+    nphys = hcore.shape[0]
+    npole = e_pole.shape[0]
+    e1 = ctypes.c_double(0.0)
+    e2 = ctypes.c_double(0.0)
+    d = h.device
+    h._check(h.lib.agf2_energy_gf(
+        h.h, nphys, _ptr(hcore, "hcore", d), _ptr(fock, "fock", d), _ptr(rdm1, "rdm1", d),
+        npole, int(nocc_pole), _ptr(e_pole, "e_pole", d), _ptr(u_pole, "u_pole", d),
+        e_se_occ.shape[0], _ptr(e_se_occ, "e_se_occ", d), _ptr(v_se_occ, "v_se_occ", d),
+        e_se_vir.shape[0], _ptr(e_se_vir, "e_se_vir", d), _ptr(v_se_vir, "v_se_vir", d),
+        ctypes.byref(e1), ctypes.byref(e2)))
+    return e1.value, e2.value
+
+
+def agf2_profile_enable(h: Handle, enable: bool = True):
+    h._check(h.lib.agf2_profile_enable(h.h, 1 if enable else 0))
+
+
+def agf2_profile_read(h: Handle) -> dict:
+    """{kernel class: dict(launches, ms, flops, bytes)} accumulated since the
+    profiler was enabled."""
+    n = h.lib.agf2_profile_count(h.h)
+    if n < 0:
+        h._check(n)
+    out = {}
+    for i in range(n):
+        name = ctypes.c_char_p()
+        launches = ctypes.c_long(0)
+        ms = ctypes.c_double(0.0)
+        fl = ctypes.c_double(0.0)
+        by = ctypes.c_double(0.0)
+        h._check(h.lib.agf2_profile_get(h.h, i, ctypes.byref(name), ctypes.byref(launches),
+                                        ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)))
+        out[name.value.decode()] = dict(launches=launches.value, ms=ms.value, flops=fl.value,
+                                        bytes=by.value)
+    return out

@@ -1,0 +1,143 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/agf2.h"
+
+namespace agf2 {
+
+// Error carried from the implementation to the C boundary.
+struct Error {
+  agf2_status status;
+  std::string msg;
+};
+
+#define AGF2_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw ::agf2::Error{AGF2_ERR_HIP, std::string(#call) + ": " +           \
+                                            hipGetErrorString(e_)};           \
+  } while (0)
+
+#define AGF2_CHECK_LAUNCH() AGF2_HIP(hipGetLastError())
+
+#define AGF2_REQUIRE(cond, text)                                              \
+  do {                                                                        \
+    if (!(cond)) throw ::agf2::Error{AGF2_ERR_ARG, text};                     \
+  } while (0)
+
+// A device buffer that grows on demand and is reused across calls.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  void* get(size_t need);
+  template <class T> T* as(size_t n) { return static_cast<T*>(get(n * sizeof(T))); }
+  void release();
+};
+
+struct Handle;
+
+// v_mfma_f64_16x16x4f64 lane layout (gfx950): lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; accumulator register r of lane l holds
+// D[l / 16 + 4 r][l % 16].
+
+// ---------------------------------------------------------------- GEMM
+// C[b][s][m][n] = alpha * sum_{r in split s} sum_k A(b,r,m,k) B(b,r,k,n)
+//               + beta * C[b][s][m][n]
+// Addresses: A + b*sAb + r*sAr + m*sAm + k*sAk (likewise B and C). The reduce
+// index r runs over [0, R) and is divided into `nsplit` contiguous ranges, one
+// per output slice s (slice stride sCs). Either sAm or sAk must be 1, and
+// either sBn or sBk must be 1 (the contiguous one is used for coalescing).
+struct Gemm {
+  int M = 0, N = 0, K = 0;
+  int batch = 1, R = 1, nsplit = 1;
+  const double* A = nullptr;
+  long sAb = 0, sAr = 0, sAm = 0, sAk = 0;
+  const double* B = nullptr;
+  long sBb = 0, sBr = 0, sBk = 0, sBn = 0;
+  double* C = nullptr;
+  long sCb = 0, sCs = 0, sCm = 0, sCn = 0;
+  double alpha = 1.0, beta = 0.0;
+};
+void gemm_f64(const Gemm& g, hipStream_t stream);
+void gemm_f64_padded(const Gemm& g, int Npad, hipStream_t stream);
+
+// Sum `nslice` [rows][cols] slices spaced `slice_stride` apart into out
+// (fixed order), optionally scaling: out = scale * sum_s in[s] (+ out if add).
+void sum_slices(const double* in, long slice_stride, int nslice, long n,
+                double* out, double scale, bool add, hipStream_t stream);
+
+// ---------------------------------------------------------------- moments
+void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
+                       int nocc, const double* e, const double* u, double* m0o,
+                       double* m1o, double* m0v, double* m1v);
+void build_moments_split(Handle& h, int N, int Q, const double* L, int npole,
+                         int nocc, const double* e, const double* u,
+                         double* m0o, double* m1o, double* m0v, double* m1v);
+
+// ---------------------------------------------------------------- Fock / misc
+void fock_build(Handle& h, int N, int Q, const double* L, const double* hcore,
+                const double* D, double alpha, double* F);
+void build_hext(int N, int naux, const double* F, const double* e,
+                const double* v, double shift, double* H, hipStream_t s);
+void column_weights(int nrows_phys, int npole, const double* evecs_rowmajor,
+                    double* w, hipStream_t s);
+void extract_poles(int N, int npole, const double* evecs, double* u,
+                   hipStream_t s);
+double dot_f64(Handle& h, long n, const double* a, const double* b);
+void axpby_f64(long n, double a, const double* x, double b, double* y,
+               hipStream_t s);
+void symmetrize_f64(int N, double* A, hipStream_t s);
+
+// Per-kernel-class timing: hipEvents recorded on the handle's stream around
+// each launch of a class, with the launch's algorithmic flop and byte counts.
+struct ProfRecord {
+  std::string name;
+  hipEvent_t start, stop;
+  double flops, bytes;
+};
+struct ProfTotal {
+  long launches = 0;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+
+struct Handle {
+  int device = 0;
+  bool profiling = false;
+  std::vector<ProfRecord> prof_pending;
+  std::map<std::string, ProfTotal> prof_total;
+  std::vector<std::string> prof_names;   // stable storage for returned names
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  rocblas_handle blas = nullptr;
+  std::string last_error;
+  // workspace pools
+  DevBuf ws_moments[8];
+  DevBuf ws_fock[8];
+  DevBuf ws_misc[8];
+  DevBuf ws_red;
+  double* host_red = nullptr;   // pinned scratch for small reductions
+  size_t host_red_n = 0;
+  ~Handle();
+};
+
+// RAII scope: records start/stop events around the enclosed launches when
+// profiling is on.
+struct ProfScope {
+  Handle& h;
+  ProfRecord rec;
+  bool on;
+  ProfScope(Handle& hh, const char* name, double flops, double bytes);
+  ~ProfScope();
+};
+
+}  // namespace agf2

@@ -1,0 +1,450 @@
+// FP64 self-energy moment build (zeroth/first moment equations; lesser and
+// greater parts of the second-order self-energy).
+//
+// For one part, with "pair" poles p, q (occupied for the lesser part, virtual
+// for the greater part) and "inner" poles c of the other kind:
+//   X^{pq}[x][c] = (xp|qc) = sum_Q R[p][x][Q] S[q][c][Q]
+//   U0 = sum_{p,q} X^{pq} (2 X^{pq} - X^{qp})^T
+//   U1 = same with the weight e_p + e_q - e_c on column c
+// Pairing (p,q) with (q,p) turns the summand into a sum of squares,
+//   X^{pq}(2X^{pq}-X^{qp})^T + X^{qp}(2X^{qp}-X^{pq})^T
+//     = 1/2 (X^{pq}+X^{qp})(...)^T + 3/2 (X^{pq}-X^{qp})(...)^T,
+// and X^{pp} X^{pp T} for p = q. The build therefore runs in two kernels:
+//   slab:  one workgroup owns a pair p<q and an (x, c) tile. It forms
+//          X^{pq} and X^{qp} for that tile in two MFMA accumulators over Q
+//          (LDS-staged operand tiles), so each exchange partner (xq|pc)
+//          sits in the same lane and register as its direct term (xp|qc).
+//          The epilogue writes the columns sqrt(1/2)(X^{pq}+X^{qp}) and
+//          sqrt(3/2)(X^{pq}-X^{qp}) of Z and their weight.
+//   syrk:  U0 += Z Z^T and U1 += Z diag(w) Z^T on lower-triangle tiles,
+//          split over K into per-split float64 partials (no atomics).
+// Z is produced and consumed in chunks of whole pairs; partials are summed
+// in a fixed order at the end, so results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+
+#include "agf2_internal.h"
+
+namespace agf2 {
+void gemm_f64_padded(const Gemm& g, int Npad, hipStream_t stream);
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int TB = 64, BK = 16, NT = 256, LD = TB + 1;
+
+// Round-robin dispatch places workgroup w on XCD w % 8; remap so that each
+// XCD receives one contiguous range of logical tiles (operand reuse in its L2).
+__device__ __forceinline__ long xcd_remap(long w, long G) {
+  const long per = G / 8, rem = G % 8;
+  const long xcd = w % 8, slot = w / 8;
+  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+struct SlabArgs {
+  const double* R; long sRp, sRx;   // R[p][x][Q]
+  const double* S; long sSp, sSc;   // S[q][c][Q]
+  const double* ep; const double* ec;
+  int N, nc, Qp;
+  const int* pi; const int* pj; const long* pcol;
+  int pair0, npairs; long col_base;
+  double* Z; long ldz; double* w;
+  int tiles_x, tiles_c;
+};
+
+__global__ __launch_bounds__(NT) void slab_f64_kernel(SlabArgs a) {
+  __shared__ double A1[2][BK][LD], A2[2][BK][LD], B1[2][BK][LD], B2[2][BK][LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long G = (long)a.npairs * a.tiles_x * a.tiles_c;
+  const long logical = xcd_remap(blockIdx.x, G);
+  const int per_pair = a.tiles_x * a.tiles_c;
+  const int P = a.pair0 + (int)(logical / per_pair);
+  const int rem = (int)(logical % per_pair);
+  const int xt = rem % a.tiles_x, ct = rem / a.tiles_x;
+  const int p = a.pi[P], q = a.pj[P];
+  const bool diag = (p == q);
+  const int x0 = xt * TB, c0 = ct * TB;
+
+  const double* Rp = a.R + (long)p * a.sRp;
+  const double* Rq = a.R + (long)q * a.sRp;
+  const double* Sq = a.S + (long)q * a.sSp;
+  const double* Sp = a.S + (long)p * a.sSp;
+
+  // loader: thread -> k = tid % 16, rows tid/16 + 16 i
+  const int lk = tid & 15, lr = tid >> 4;
+  double r1[4], r2[4], s1[4], s2[4];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int x = x0 + lr + 16 * i, c = c0 + lr + 16 * i, k = kb + lk;
+      const bool xin = x < a.N, cin = c < a.nc;
+      r1[i] = xin ? Rp[(long)x * a.sRx + k] : 0.0;
+      s1[i] = cin ? Sq[(long)c * a.sSc + k] : 0.0;
+      if (!diag) {
+        r2[i] = xin ? Rq[(long)x * a.sRx + k] : 0.0;
+        s2[i] = cin ? Sp[(long)c * a.sSc + k] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      A1[buf][lk][lr + 16 * i] = r1[i];
+      B1[buf][lk][lr + 16 * i] = s1[i];
+      if (!diag) {
+        A2[buf][lk][lr + 16 * i] = r2[i];
+        B2[buf][lk][lr + 16 * i] = s2[i];
+      }
+    }
+  };
+
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int fr = lane & 15, fk = lane >> 4;
+  d4 c1[2][2], c2[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      c1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      c2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  const int nsteps = a.Qp / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int step = 0; step < nsteps; ++step) {
+    const int buf = step & 1;
+    if (step + 1 < nsteps) load((step + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double x1[2], y1[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) x1[i] = A1[buf][kk + fk][wm + 16 * i + fr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) y1[j] = B1[buf][kk + fk][wn + 16 * j + fr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          c1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[i], y1[j], c1[i][j], 0, 0, 0);
+      if (!diag) {
+        double x2[2], y2[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) x2[i] = A2[buf][kk + fk][wm + 16 * i + fr];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) y2[j] = B2[buf][kk + fk][wn + 16 * j + fr];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            c2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x2[i], y2[j], c2[i][j], 0, 0, 0);
+      }
+    }
+    if (step + 1 < nsteps) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  const long col0 = a.pcol[P] - a.col_base;
+  const double cp = 0.70710678118654752440;   // sqrt(1/2)
+  const double cm = 1.22474487139158904910;   // sqrt(3/2)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + wm + 16 * i + fk + 4 * r;
+        const int c = c0 + wn + 16 * j + fr;
+        if (x >= a.N || c >= a.nc) continue;
+        double* z = a.Z + (long)x * a.ldz + col0 + c;
+        if (diag) {
+          z[0] = c1[i][j][r];
+        } else {
+          const double u = c1[i][j][r], v = c2[i][j][r];
+          z[0] = cp * (u + v);
+          z[a.nc] = cm * (u - v);
+        }
+      }
+  if (xt == 0 && tid < TB) {
+    const int c = c0 + tid;
+    if (c < a.nc) {
+      const double wgt = a.ep[p] + a.ep[q] - a.ec[c];
+      a.w[col0 + c] = wgt;
+      if (!diag) a.w[col0 + a.nc + c] = wgt;
+    }
+  }
+}
+
+struct SyrkArgs {
+  const double* Z; long ldz; const double* w;
+  int N; long K; long kper;
+  double* part; long part_stride;   // per split: [2][N][N]
+  int tiles;                        // lower-triangle tile count
+};
+
+__global__ __launch_bounds__(NT) void syrk_f64_kernel(SyrkArgs a) {
+  __shared__ double X[2][BK][LD], Y[2][BK][LD], W[2][BK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // tile -> (xt >= yt)
+  const int t = blockIdx.x;
+  int xt = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((xt + 1) * (xt + 2) / 2 <= t) ++xt;
+  while (xt * (xt + 1) / 2 > t) --xt;
+  const int yt = t - xt * (xt + 1) / 2;
+  const int s = blockIdx.y;
+  const long k0 = (long)s * a.kper, k1 = std::min(a.K, k0 + a.kper);
+  const int x0 = xt * TB, y0 = yt * TB;
+  const int lk = tid & 15, lr = tid >> 4;
+  double rx[4], ry[4], rw = 0.0;
+  auto load = [&](long kb) {
+    const long k = kb + lk;
+    const bool kin = k < k1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int x = x0 + lr + 16 * i, y = y0 + lr + 16 * i;
+      rx[i] = (kin && x < a.N) ? a.Z[(long)x * a.ldz + k] : 0.0;
+      ry[i] = (kin && y < a.N) ? a.Z[(long)y * a.ldz + k] : 0.0;
+    }
+    if (tid < BK) rw = kin ? a.w[k] : 0.0;
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      X[buf][lk][lr + 16 * i] = rx[i];
+      Y[buf][lk][lr + 16 * i] = ry[i];
+    }
+    if (tid < BK) W[buf][tid] = rw;
+  };
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int fr = lane & 15, fk = lane >> 4;
+  d4 u0[2][2], u1[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      u0[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      u1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const long nsteps = (k1 > k0) ? (k1 - k0 + BK - 1) / BK : 0;
+  if (nsteps > 0) {
+    load(k0);
+    store(0);
+    __syncthreads();
+  }
+  for (long step = 0; step < nsteps; ++step) {
+    const int buf = step & 1;
+    if (step + 1 < nsteps) load(k0 + (step + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const double wk = W[buf][kk + fk];
+      double xa[2], xw[2], yb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        xa[i] = X[buf][kk + fk][wm + 16 * i + fr];
+        xw[i] = xa[i] * wk;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) yb[j] = Y[buf][kk + fk][wn + 16 * j + fr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          u0[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], yb[j], u0[i][j], 0, 0, 0);
+          u1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xw[i], yb[j], u1[i][j], 0, 0, 0);
+        }
+    }
+    if (step + 1 < nsteps) store(buf ^ 1);
+    __syncthreads();
+  }
+  if (nsteps == 0) return;
+  double* P0 = a.part + (long)s * a.part_stride;
+  double* P1 = P0 + (long)a.N * a.N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + wm + 16 * i + fk + 4 * r;
+        const int y = y0 + wn + 16 * j + fr;
+        if (x >= a.N || y >= a.N) continue;
+        const long o = (long)x * a.N + y;
+        P0[o] += u0[i][j][r];
+        P1[o] += u1[i][j][r];
+      }
+}
+
+// U[x][y] = U[y][x] = sum_s part[s][m][x][y] for x >= y (fixed order).
+__global__ void reduce_sym_kernel(const double* part, long part_stride, int nsplit,
+                                  int N, double* U0, double* U1) {
+  const long n = (long)N * N;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < n;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int x = (int)(idx / N), y = (int)(idx % N);
+    if (x < y) continue;
+    double s0 = 0.0, s1 = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+      s0 += part[s * part_stride + idx];
+      s1 += part[s * part_stride + n + idx];
+    }
+    U0[(long)x * N + y] = s0; U0[(long)y * N + x] = s0;
+    U1[(long)x * N + y] = s1; U1[(long)y * N + x] = s1;
+  }
+}
+
+struct PairTable {
+  std::vector<int> pi, pj;
+  std::vector<long> col;   // column offset of each pair (prefix sum of widths)
+};
+
+PairTable make_pairs(int np, int nc) {
+  PairTable t;
+  long c = 0;
+  for (int p = 0; p < np; ++p)
+    for (int q = p; q < np; ++q) {
+      t.pi.push_back(p); t.pj.push_back(q); t.col.push_back(c);
+      c += (p == q) ? nc : 2L * nc;
+    }
+  t.col.push_back(c);
+  return t;
+}
+
+}  // namespace
+
+static long ndiag(const PairTable& t, int P0, int P1) {
+  long n = 0;
+  for (int P = P0; P < P1; ++P) n += (t.pi[P] == t.pj[P]);
+  return n;
+}
+
+// One part (lesser or greater) of the moment build.
+static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, long sRp,
+                             long sRx, const double* S, long sSp, long sSc,
+                             const double* ep, int np, const double* ec, int nc,
+                             double* U0, double* U1, int slot) {
+  hipStream_t st = h.stream;
+  const long nn = (long)N * N;
+  if (np == 0 || nc == 0) {
+    AGF2_HIP(hipMemsetAsync(U0, 0, nn * sizeof(double), st));
+    AGF2_HIP(hipMemsetAsync(U1, 0, nn * sizeof(double), st));
+    return;
+  }
+  PairTable t = make_pairs(np, nc);
+  const int npairs = (int)t.pi.size();
+  int* d_pi = h.ws_moments[slot].as<int>(2L * npairs + 2 * (npairs + 1));
+  int* d_pj = d_pi + npairs;
+  long* d_col = reinterpret_cast<long*>(h.ws_moments[slot + 1].get((npairs + 1) * sizeof(long)));
+  AGF2_HIP(hipMemcpyAsync(d_pi, t.pi.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
+  AGF2_HIP(hipMemcpyAsync(d_pj, t.pj.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
+  AGF2_HIP(hipMemcpyAsync(d_col, t.col.data(), (npairs + 1) * sizeof(long), hipMemcpyHostToDevice, st));
+
+  // Z chunk capacity: whole pairs, at most ~1 GiB of Z
+  const long cap_bytes = 1L << 30;
+  long kcap = std::max<long>(2L * nc, cap_bytes / (8L * N));
+  kcap = std::min<long>(kcap, t.col.back());
+  kcap = (kcap + BK - 1) / BK * BK;
+  double* Z = h.ws_moments[4].as<double>((long)N * kcap + kcap);
+  double* w = Z + (long)N * kcap;
+
+  const int tiles_n = (N + TB - 1) / TB;
+  const int nlower = tiles_n * (tiles_n + 1) / 2;
+  const int nsplit_max = std::max(1, std::min(64, (2048 + nlower - 1) / nlower));
+  const long part_stride = 2 * nn;
+  double* part = h.ws_moments[5].as<double>(part_stride * nsplit_max);
+  AGF2_HIP(hipMemsetAsync(part, 0, part_stride * nsplit_max * sizeof(double), st));
+
+  const int tiles_x = tiles_n, tiles_c = (nc + TB - 1) / TB;
+  int P0 = 0;
+  while (P0 < npairs) {
+    int P1 = P0;
+    while (P1 < npairs && t.col[P1 + 1] - t.col[P0] <= kcap) ++P1;
+    if (P1 == P0) P1 = P0 + 1;
+    const long Kc = t.col[P1] - t.col[P0];
+
+    SlabArgs sa;
+    sa.R = R; sa.sRp = sRp; sa.sRx = sRx;
+    sa.S = S; sa.sSp = sSp; sa.sSc = sSc;
+    sa.ep = ep; sa.ec = ec; sa.N = N; sa.nc = nc; sa.Qp = Qp;
+    sa.pi = d_pi; sa.pj = d_pj; sa.pcol = d_col;
+    sa.pair0 = P0; sa.npairs = P1 - P0; sa.col_base = t.col[P0];
+    sa.Z = Z; sa.ldz = kcap; sa.w = w;
+    sa.tiles_x = tiles_x; sa.tiles_c = tiles_c;
+    const long G = (long)sa.npairs * tiles_x * tiles_c;
+    {
+      // algorithmic: 2 N nc Q per (p,q) slab, two slabs per off-diagonal pair;
+      // bytes: the Z chunk and its weights written once
+      const double slabs = (double)(2 * (P1 - P0)) - (double)ndiag(t, P0, P1);
+      ProfScope ps(h, "moments.slab", slabs * 2.0 * N * nc * Q, 8.0 * (N + 1.0) * Kc);
+      hipLaunchKernelGGL(slab_f64_kernel, dim3((unsigned)G), dim3(NT), 0, st, sa);
+      AGF2_CHECK_LAUNCH();
+    }
+
+    int nsplit = (int)std::min<long>(nsplit_max, std::max<long>(1, Kc / 256));
+    long kper = (Kc + nsplit - 1) / nsplit;
+    kper = (kper + BK - 1) / BK * BK;
+    nsplit = (int)((Kc + kper - 1) / kper);
+    SyrkArgs ya;
+    ya.Z = Z; ya.ldz = kcap; ya.w = w; ya.N = N; ya.K = Kc; ya.kper = kper;
+    ya.part = part; ya.part_stride = part_stride; ya.tiles = nlower;
+    {
+      // algorithmic: lower triangles of two symmetric N x N products over Kc
+      ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 1.0) * Kc);
+      hipLaunchKernelGGL(syrk_f64_kernel, dim3(nlower, nsplit), dim3(NT), 0, st, ya);
+      AGF2_CHECK_LAUNCH();
+    }
+    P0 = P1;
+  }
+  const long blocks = std::min<long>((nn + 255) / 256, 4096);
+  ProfScope ps(h, "moments.reduce", 0.0, 8.0 * (2.0 * nsplit_max + 2.0) * nn);
+  hipLaunchKernelGGL(reduce_sym_kernel, dim3(blocks), dim3(256), 0, st, part,
+                     part_stride, nsplit_max, N, U0, U1);
+  AGF2_CHECK_LAUNCH();
+}
+
+// Pole-basis DF tensors, Q padded to Qp (a multiple of 16) with zeros:
+//   T[p][x][Q] = sum_r u[r][p0+p] L[Q][x][r]          (p in [0, np))
+void pole_transform_f64(Handle& h, int N, int Q, int Qp, const double* L,
+                        const double* u, int npole, int p0, int np, double* T) {
+  if (np == 0) return;
+  Gemm g;
+  g.M = np; g.N = Q; g.K = N; g.batch = N;
+  g.A = u + p0; g.sAm = 1; g.sAk = npole;              // A(p, r) = u[r][p0+p]
+  g.B = L; g.sBb = N; g.sBk = 1; g.sBn = (long)N * N;  // B(r, Q) = L[Q][x][r]
+  g.C = T; g.sCb = Qp; g.sCm = (long)N * Qp; g.sCn = 1;
+  gemm_f64_padded(g, Qp, h.stream);
+}
+
+void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
+                       int nocc, const double* e, const double* u, double* m0o,
+                       double* m1o, double* m0v, double* m1v) {
+  const int o = nocc, v = npole - nocc;
+  const int Qp = (Q + BK - 1) / BK * BK;
+  double* Lxo = h.ws_moments[0].as<double>((long)o * N * Qp);
+  double* Lxv = h.ws_moments[1].as<double>((long)v * N * Qp);
+  double* Lov = h.ws_moments[2].as<double>((long)o * v * Qp);
+  {
+  ProfScope ps(h, "moments.transform",
+               2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
+               8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
+  pole_transform_f64(h, N, Q, Qp, L, u, npole, 0, o, Lxo);
+  pole_transform_f64(h, N, Q, Qp, L, u, npole, o, v, Lxv);
+  // Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q]
+  {
+    Gemm g;
+    g.M = o; g.N = Q; g.K = N; g.batch = v;
+    g.A = u; g.sAm = 1; g.sAk = npole;
+    g.B = Lxv; g.sBb = (long)N * Qp; g.sBk = Qp; g.sBn = 1;
+    g.C = Lov; g.sCb = Qp; g.sCm = (long)v * Qp; g.sCn = 1;
+    gemm_f64_padded(g, Qp, h.stream);
+  }
+  }
+  // lesser: pairs (i, j) occupied, inner a virtual; S[j][a][Q] = Lov[j][a][Q]
+  moments_part_f64(h, N, Q, Qp, Lxo, (long)N * Qp, Qp, Lov, (long)v * Qp, Qp,
+                   e, o, e + o, v, m0o, m1o, 6);
+  // greater: pairs (a, b) virtual, inner i occupied; S[b][i][Q] = Lov[i][b][Q]
+  moments_part_f64(h, N, Q, Qp, Lxv, (long)N * Qp, Qp, Lov, Qp, (long)v * Qp,
+                   e + o, v, e, o, m0v, m1v, 6);
+}
+
+}  // namespace agf2

@@ -335,3 +335,15 @@ def test_agf2_converges_and_diis_independent():
     assert abs(ha["ip"] - hb["ip"]) < 1e-6 and abs(ha["ea"] - hb["ea"]) < 1e-6
     # the pole space is N + 2N after the first compression
     assert ha["npole"] == 3 * 24
+
+
+def test_partial_pole_sums_add_up():
+    """Moments are sums over the outer summed pole: contributions of a
+    partition of the poles add up to the full moments."""
+    eps, L, nocc = small_system(nmo=9, nocc=3, naux=20)
+    e, u = syn.random_poles(8, 9, 27, 10)
+    full = O.se_moments(L, e, u, 10)
+    a = O.se_moments(L, e, u, 10, occ_sel=[0, 3, 7], vir_sel=list(range(0, 17, 2)))
+    b = O.se_moments(L, e, u, 10, occ_sel=[1, 2, 4, 5, 6, 8, 9], vir_sel=list(range(1, 17, 2)))
+    for f, x, y in zip(full, a, b):
+        assert rel(x + y, f) < 1e-14
