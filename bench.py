@@ -28,7 +28,7 @@ from paper_2106_03508_amd import synthetic as syn  # noqa: E402
 
 WORKLOADS = {"small": syn.SMALL, "medium": syn.MEDIUM, "large": syn.LARGE, "eval400": syn.EVAL400}
 SEEDS = {"small": 0, "medium": 1, "large": 2, "eval400": 20000}
-PEAK_TFLOPS = {"fp64": 78.6, "split_bf16": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "split_bf16": 2500.0, "split_fp16": 2500.0}
 
 
 def canonical_flops(N, o, v, Q):
@@ -88,7 +88,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "split_bf16"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "split_bf16", "split_fp16"])
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-occ-sample", type=int, default=1)
@@ -173,7 +173,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "bf16x3 (f32 acc, f64 sum)",
+        "dtype": {"fp64": "f64", "split_bf16": "bf16 hi/lo pairs (f32 acc, f64 sum)",
+                  "split_fp16": "f16 hi/lo pairs (f32 acc, f64 sum)"}[args.prec],
         "data": "synthetic (seeded generator; no molecular integrals)",
         "config": {"workload": f"AGF2 iteration from the mean-field reference, nmo={N} "
                                f"nocc={nocc} naux={Q} (seed {seed})",

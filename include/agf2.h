@@ -48,11 +48,18 @@ typedef enum {
   AGF2_ERR_NELEC = -6         /* electron number cannot be reached            */
 } agf2_status;
 
+/* Arithmetic of the moment build. In both split modes the pole-basis DF
+ * tensors are formed in float64, rounded to float32 and stored as 16-bit
+ * pairs x ~ hi + lo; the integral slabs take the products hi*hi + hi*lo +
+ * lo*hi on the 16-bit MFMA pipe with float32 accumulation, the moment
+ * contraction takes all four products, and float32 partial sums over bounded
+ * chunks are added into float64 with Kahan compensation. Compression, the
+ * Fock loop and the energy are float64 in every mode. */
 typedef enum {
   AGF2_FP64 = 0,        /* float64 operands, FP64 MFMA, float64 accumulation  */
-  AGF2_SPLIT_BF16 = 1   /* float32-stored operands split into bf16 hi/lo, three
-                           bf16 MFMA products, float32 accumulation over
-                           bounded chunks, float64 compensated accumulation    */
+  AGF2_SPLIT_BF16 = 1,  /* bf16 pairs (16 significant bits per value)         */
+  AGF2_SPLIT_FP16 = 2   /* fp16 pairs (22 significant bits) with power-of-two
+                           scaling of each operand row and of the slabs       */
 } agf2_precision;
 
 /* Create a handle on HIP device `device`. All work is ordered on
@@ -80,7 +87,7 @@ agf2_status agf2_synchronize(agf2_handle_t handle);
  *   m1_vir[p][q] = same summand times (e_a + e_b - e_i)
  * with (pi|ja) = sum_{Q,r,s,t} L[Q][p][r] u[r][i] L[Q][s][t] u[s][j] u[t][a].
  *
- *   prec       AGF2_FP64 or AGF2_SPLIT_BF16 (see agf2_precision).
+ *   prec       AGF2_FP64, AGF2_SPLIT_BF16 or AGF2_SPLIT_FP16.
  *   nphys      N >= 1.      naux  Q >= 1.
  *   Lpq        device, [naux][nphys][nphys], symmetric in (p,q).
  *   npole      number of Green's function poles (>= 2).

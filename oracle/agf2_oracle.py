@@ -133,6 +133,57 @@ def se_moments(L, e_pole, u_pole, nocc_pole, occ_sel=None, vir_sel=None):
     return m0o, m1o, m0v, m1v
 
 
+def se_moment_elements(L, e_pole, u_pole, nocc_pole, pairs, progress=None):
+    """Selected elements (p, q) of the four moments, each evaluated from the
+    same literal sums as se_moments but only for the physical rows p and q
+    involved (for sampling moments of systems too large to build whole).
+    progress, if given, is called with a short text now and then.
+    Returns an array [len(pairs), 4] of (U0<, U1<, U0>, U1>) values."""
+    Q = L.shape[0]
+    eo = e_pole[:nocc_pole]
+    ev = e_pole[nocc_pole:]
+    o, v = eo.shape[0], ev.shape[0]
+    uo = u_pole[:, :nocc_pole]
+    uv = u_pole[:, nocc_pole:]
+    rows = sorted({p for p, _ in pairs} | {q for _, q in pairs})
+    Lr = L[:, rows, :]                                          # [Q, rows, N]
+    Lxo_r = np.einsum("Qxr,ri->Qxi", Lr, uo, optimize=True)     # (xi|Q) for the rows
+    Lxv_r = np.einsum("Qxr,ra->Qxa", Lr, uv, optimize=True)
+    # (ia|Q) = u_i^T L_Q u_a, one Q at a time
+    Lov = np.empty((Q, o, v))
+    for q in range(Q):
+        Lov[q] = uo.T @ (L[q] @ uv)
+        if progress and q % 500 == 499:
+            progress(f"oracle transform {q + 1}/{Q}")
+    Lov_m = Lov.reshape(Q, o * v)
+    Lvo_m = np.ascontiguousarray(Lov.transpose(0, 2, 1).reshape(Q, v * o))
+    Lov_i = np.ascontiguousarray(Lov.transpose(1, 0, 2))       # [o][Q][v]
+    Lov_a = np.ascontiguousarray(Lov.transpose(2, 0, 1))       # [v][Q][o]
+    pos = {x: k for k, x in enumerate(rows)}
+    out = np.zeros((len(pairs), 4))
+    w_o = eo[:, None, None] + eo[None, :, None] - ev[None, None, :]   # [i, j, a]
+    w_v = ev[:, None, None] + ev[None, :, None] - eo[None, None, :]   # [a, b, i]
+    for k, (p, q) in enumerate(pairs):
+        rp, rq = pos[p], pos[q]
+        # lesser: X[i, j, a] = (pi|ja), Y[i, j, a] = (qi|ja), E[i, j, a] = (qj|ia)
+        X = (np.ascontiguousarray(Lxo_r[:, rp, :].T) @ Lov_m).reshape(o, o, v)
+        Y = (np.ascontiguousarray(Lxo_r[:, rq, :].T) @ Lov_m).reshape(o, o, v)
+        E = np.matmul(np.ascontiguousarray(Lxo_r[:, rq, :].T), Lov_i)  # [i][j][a]
+        t = 2.0 * Y - E
+        out[k, 0] = np.sum(X * t)
+        out[k, 1] = np.sum(X * w_o * t)
+        # greater: X[a, b, i] = (pa|bi), Y[a, b, i] = (qa|bi), E[a, b, i] = (qb|ai)
+        X = (np.ascontiguousarray(Lxv_r[:, rp, :].T) @ Lvo_m).reshape(v, v, o)
+        Y = (np.ascontiguousarray(Lxv_r[:, rq, :].T) @ Lvo_m).reshape(v, v, o)
+        E = np.matmul(np.ascontiguousarray(Lxv_r[:, rq, :].T), Lov_a)  # [a][b][i]
+        t = 2.0 * Y - E
+        out[k, 2] = np.sum(X * t)
+        out[k, 3] = np.sum(X * w_v * t)
+        if progress:
+            progress(f"oracle element {k + 1}/{len(pairs)}")
+    return out
+
+
 def se_moments_4index(eri, e_pole, u_pole, nocc_pole):
     """The same moments from explicit four-index integrals, transformed to
     the pole basis and summed with plain loops over the summed poles.

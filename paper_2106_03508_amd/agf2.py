@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libagf2.so")
 
 AGF2_FP64 = 0
 AGF2_SPLIT_BF16 = 1
-PRECISIONS = {"fp64": AGF2_FP64, "split_bf16": AGF2_SPLIT_BF16}
+AGF2_SPLIT_FP16 = 2
+PRECISIONS = {"fp64": AGF2_FP64, "split_bf16": AGF2_SPLIT_BF16, "split_fp16": AGF2_SPLIT_FP16}
 
 STATUS = {0: "AGF2_OK", -1: "AGF2_ERR_ARG", -2: "AGF2_ERR_HIP", -3: "AGF2_ERR_NOMEM",
           -4: "AGF2_ERR_NOT_PD", -5: "AGF2_ERR_NO_CONVERGE", -6: "AGF2_ERR_NELEC"}

@@ -641,9 +641,9 @@ agf2_status agf2_build_moments(agf2_handle_t hh, agf2_precision prec, int nphys,
     if (prec == AGF2_FP64)
       build_moments_f64(h, nphys, naux, Lpq, npole, nocc_pole, e_pole, u_pole, m0_occ,
                         m1_occ, m0_vir, m1_vir);
-    else if (prec == AGF2_SPLIT_BF16)
+    else if (prec == AGF2_SPLIT_BF16 || prec == AGF2_SPLIT_FP16)
       build_moments_split(h, nphys, naux, Lpq, npole, nocc_pole, e_pole, u_pole, m0_occ,
-                          m1_occ, m0_vir, m1_vir);
+                          m1_occ, m0_vir, m1_vir, prec == AGF2_SPLIT_FP16);
     else
       throw Error{AGF2_ERR_ARG, "unknown precision mode"};
   });

@@ -82,7 +82,8 @@ void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
                        double* m1o, double* m0v, double* m1v);
 void build_moments_split(Handle& h, int N, int Q, const double* L, int npole,
                          int nocc, const double* e, const double* u,
-                         double* m0o, double* m1o, double* m0v, double* m1v);
+                         double* m0o, double* m1o, double* m0v, double* m1v,
+                         bool fp16);
 
 // ---------------------------------------------------------------- Fock / misc
 void fock_build(Handle& h, int N, int Q, const double* L, const double* hcore,

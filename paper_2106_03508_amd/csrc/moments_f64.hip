@@ -293,6 +293,19 @@ __global__ void reduce_sym_kernel(const double* part, long part_stride, int nspl
   }
 }
 
+}  // namespace
+
+void reduce_moment_partials(const double* part, long part_stride, int nsplit, int N,
+                            double* U0, double* U1, hipStream_t st) {
+  const long nn = (long)N * N;
+  const long blocks = std::min<long>((nn + 255) / 256, 4096);
+  hipLaunchKernelGGL(reduce_sym_kernel, dim3(blocks), dim3(256), 0, st, part, part_stride,
+                     nsplit, N, U0, U1);
+  AGF2_CHECK_LAUNCH();
+}
+
+namespace {
+
 struct PairTable {
   std::vector<int> pi, pj;
   std::vector<long> col;   // column offset of each pair (prefix sum of widths)
@@ -395,11 +408,8 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
     }
     P0 = P1;
   }
-  const long blocks = std::min<long>((nn + 255) / 256, 4096);
   ProfScope ps(h, "moments.reduce", 0.0, 8.0 * (2.0 * nsplit_max + 2.0) * nn);
-  hipLaunchKernelGGL(reduce_sym_kernel, dim3(blocks), dim3(256), 0, st, part,
-                     part_stride, nsplit_max, N, U0, U1);
-  AGF2_CHECK_LAUNCH();
+  reduce_moment_partials(part, part_stride, nsplit_max, N, U0, U1, st);
 }
 
 // Pole-basis DF tensors, Q padded to Qp (a multiple of 16) with zeros:

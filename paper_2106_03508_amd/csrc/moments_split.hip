@@ -1,14 +1,786 @@
-// Split-precision moment build (bf16 hi/lo products on MFMA).
+// Split-precision self-energy moment build (same mathematics as the FP64
+// build; see moments_f64.hip for the pairing of (p,q) with (q,p)).
+//
+// Precision scheme (two storage formats, same kernels):
+//   - the pole-basis DF tensors are formed in float64, rounded to float32 and
+//     stored as 16-bit pairs x ~ hi + lo (hi = r(x), lo = r(x - hi)) where r
+//     rounds to bf16 (8 significant bits) or to fp16 (11 significant bits);
+//   - fp16 operands are scaled by powers of two first (one exponent per pole
+//     row of R, one per row of S, and one for all of Z and of w*Z), chosen
+//     from exact maxima or a Cauchy-Schwarz bound so that nothing overflows;
+//     the scales are undone exactly in float32/float64;
+//   - slab products a*b are evaluated as hi*hi + hi*lo + lo*hi with
+//     v_mfma_f32_16x16x32_{bf16,f16} (float32 accumulation over Q);
+//   - the slab kernel writes the Z columns and their weighted copies w*Z as
+//     16-bit pairs; the SYRK kernel takes all four products of Z (the lo*lo
+//     term of a square is never negative, so dropping it would bias U0),
+//     accumulates in float32 over chunks of KC columns and folds each chunk
+//     into float64 accumulators with Kahan compensation; per-split float64
+//     partials are summed in a fixed order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
 #include "agf2_internal.h"
 
 namespace agf2 {
 
+void reduce_moment_partials(const double* part, long part_stride, int nsplit, int N,
+                            double* U0, double* U1, hipStream_t st);
+void pole_transform_f64(Handle& h, int N, int Q, int Qp, const double* L, const double* u,
+                        int npole, int p0, int np, double* T);
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+typedef u16 u16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int KS = 32;        // k depth of one MFMA step
+constexpr int KV = KS / 8;    // 16-byte vectors per row per step
+constexpr int KVP = KV + 1;   // padded LDS row (conflict-free fragment reads)
+constexpr int NT = 256;
+constexpr int KC_STEPS = 8;   // float32 accumulation chunk of the SYRK (8 x 32 columns)
+
+// v_mfma_f32_16x16x32_{bf16,f16} (gfx950): lane l supplies A[l % 16][8 (l / 16) + t]
+// and B[8 (l / 16) + t][l % 16], t = 0..7; accumulator register r of lane l
+// holds D[4 (l / 16) + r][l % 16].
+__device__ __forceinline__ int crow(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+template <bool F16>
+__device__ __forceinline__ f4 mfma(const u16x8& a, const u16x8& b, const f4& c) {
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// float -> bf16 bits, round to nearest even
+__device__ __forceinline__ u16 f2bf(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (u16)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float((unsigned)b << 16); }
+
+template <bool F16>
+__device__ __forceinline__ void split(float x, u16& hi, u16& lo) {
+  if constexpr (F16) {
+    const _Float16 h = (_Float16)x;
+    const _Float16 l = (_Float16)(x - (float)h);
+    hi = __builtin_bit_cast(u16, h);
+    lo = __builtin_bit_cast(u16, l);
+  } else {
+    hi = f2bf(x);
+    lo = f2bf(x - bf2f(hi));
+  }
+}
+
+__device__ __forceinline__ long xcd_remap(long w, long G) {
+  const long per = G / 8, rem = G % 8;
+  const long xcd = w % 8, slot = w / 8;
+  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+// Largest exponent any scaled operand may reach: |x| * 2^scale < 2^EMAX
+// keeps fp16 hi (max 65504) finite with headroom.
+constexpr int EMAX = 13;
+
+// Per-row statistics of float64 rows of length Q. Row r = (ia, ib), ib
+// fastest; its group is g = ia * gsa + ib * gsb. gexp[g] receives the
+// largest exponent e with |x| < 2^e over the group (integer atomicMax); nrm2
+// receives the largest squared row 2-norm (as the ordered bit pattern of a
+// non-negative double).
+__global__ void row_stats_kernel(const double* in, long s_in_a, long s_in_b, int nb, int Q,
+                                 long rows, long gsa, long gsb, int* gexp,
+                                 unsigned long long* nrm2) {
+  const int lane = threadIdx.x & 63;
+  const long wave0 = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6;
+  const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+  for (long r = wave0; r < rows; r += nwaves) {
+    const long ia = r / nb, ib = r % nb;
+    const double* row = in + ia * s_in_a + ib * s_in_b;
+    double mx = 0.0, ss = 0.0;
+    for (int q = lane; q < Q; q += 64) {
+      const double x = row[q];
+      mx = fmax(mx, fabs(x));
+      ss += x * x;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      mx = fmax(mx, __shfl_down(mx, off, 64));
+      ss += __shfl_down(ss, off, 64);
+    }
+    if (lane == 0) {
+      int e = 0;
+      if (mx > 0.0) frexp(mx, &e);
+      else e = -1000;
+      atomicMax(&gexp[ia * gsa + ib * gsb], e);
+      atomicMax(nrm2, (unsigned long long)__double_as_longlong(ss));
+    }
+  }
+}
+
+// float64 rows -> 16-bit hi/lo rows, zero padded from Q to Qs, scaled by
+// 2^(EMAX - gexp[ia * gsa + ib * gsb]) when gexp is given (fp16 format).
+// Column qq of the output holds input column perm[qq] (perm[qq] < 0: zero).
+template <bool F16>
+__global__ void split_rows_kernel(const double* in, long s_in_a, long s_in_b, int nb,
+                                  const int* perm, u16* hi, u16* lo, long s_out_a,
+                                  long s_out_b, int Qs, long rows, const int* gexp, long gsa,
+                                  long gsb) {
+  const long tot = rows * Qs;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long r = idx / Qs;
+    const int q = (int)(idx % Qs);
+    const long ia = r / nb, ib = r % nb;
+    const int src = perm[q];
+    double x = src >= 0 ? in[ia * s_in_a + ib * s_in_b + src] : 0.0;
+    if (gexp) x = ldexp(x, EMAX - gexp[ia * gsa + ib * gsb]);
+    u16 h, l;
+    split<F16>((float)x, h, l);
+    const long o = ia * s_out_a + ib * s_out_b + q;
+    hi[o] = h;
+    lo[o] = l;
+  }
+}
+
+struct SlabArgs {
+  const u16* Rh; const u16* Rl; long sRp, sRx;   // R[p][x][Qs]
+  const u16* Sh; const u16* Sl; long sSp, sSc;   // S[q][c][Qs]
+  const int* eR;                                 // fp16: exponent of R row group p
+  const int* eS; long sEp, sEc;                  // fp16: exponent of S row (q, c)
+  float zscale, wscale;                          // 2^fZ, 2^fW (1 for bf16)
+  const double* ep; const double* ec;
+  int N, nc, Qs;
+  const int* pi; const int* pj; const long* pcol;
+  int pair0, npairs; long col_base;
+  u16* Zh; u16* Zl; u16* Wh; u16* Wl; long ldz;
+  int tiles_x, tiles_c;
+};
+
+constexpr int TX = 128;   // x rows per slab workgroup (32 per wave)
+
+template <int CB, bool F16>
+__global__ __launch_bounds__(NT) void slab_split_kernel(SlabArgs a) {
+  constexpr int TC = 16 * CB;
+  __shared__ u16x8 sA[4][TX][KVP];   // R[p] hi, R[p] lo, R[q] hi, R[q] lo
+  __shared__ u16x8 sB[4][TC][KVP];   // S[q] hi, S[q] lo, S[p] hi, S[p] lo
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long G = (long)a.npairs * a.tiles_x * a.tiles_c;
+  const long logical = xcd_remap(blockIdx.x, G);
+  const int per_pair = a.tiles_x * a.tiles_c;
+  const int P = a.pair0 + (int)(logical / per_pair);
+  const int rem = (int)(logical % per_pair);
+  const int xt = rem % a.tiles_x, ct = rem / a.tiles_x;
+  const int p = a.pi[P], q = a.pj[P];
+  const bool diag = (p == q);
+  const int x0 = xt * TX, c0 = ct * TC;
+  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  u16x8 ra[8], rb[CB];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int idx = tid + NT * i;
+      const int arr = idx / (TX * KV), rr = (idx / KV) % TX, kv = idx % KV;
+      const int x = x0 + rr;
+      const bool use = x < a.N && (arr < 2 || !diag);
+      const u16* base = (arr & 1) ? a.Rl : a.Rh;
+      const int pole = arr < 2 ? p : q;
+      ra[i] = use ? *reinterpret_cast<const u16x8*>(base + (long)pole * a.sRp + (long)x * a.sRx +
+                                                    kb + 8 * kv)
+                  : zero8;
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int idx = tid + NT * i;
+      const int arr = idx / (TC * KV), rr = (idx / KV) % TC, kv = idx % KV;
+      const int c = c0 + rr;
+      const bool use = c < a.nc && (arr < 2 || !diag);
+      const u16* base = (arr & 1) ? a.Sl : a.Sh;
+      const int pole = arr < 2 ? q : p;
+      rb[i] = use ? *reinterpret_cast<const u16x8*>(base + (long)pole * a.sSp + (long)c * a.sSc +
+                                                    kb + 8 * kv)
+                  : zero8;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int idx = tid + NT * i;
+      sA[idx / (TX * KV)][(idx / KV) % TX][idx % KV] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int idx = tid + NT * i;
+      sB[idx / (TC * KV)][(idx / KV) % TC][idx % KV] = rb[i];
+    }
+  };
+
+  const int fr = lane & 15, fk = lane >> 4;
+  const int wr = 32 * wave;
+  f4 c1[2][CB], c2[2][CB];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      c1[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      c2[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  const int nsteps = a.Qs / KS;
+  load(0);
+  for (int step = 0; step < nsteps; ++step) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (step + 1 < nsteps) load((step + 1) * KS);
+    u16x8 ah1[2], al1[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ah1[i] = sA[0][wr + 16 * i + fr][fk];
+      al1[i] = sA[1][wr + 16 * i + fr][fk];
+    }
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const u16x8 bh = sB[0][16 * j + fr][fk], bl = sB[1][16 * j + fr][fk];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        c1[i][j] = mfma<F16>(ah1[i], bh, c1[i][j]);
+        c1[i][j] = mfma<F16>(ah1[i], bl, c1[i][j]);
+        c1[i][j] = mfma<F16>(al1[i], bh, c1[i][j]);
+      }
+    }
+    if (!diag) {
+      u16x8 ah2[2], al2[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ah2[i] = sA[2][wr + 16 * i + fr][fk];
+        al2[i] = sA[3][wr + 16 * i + fr][fk];
+      }
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const u16x8 bh = sB[2][16 * j + fr][fk], bl = sB[3][16 * j + fr][fk];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          c2[i][j] = mfma<F16>(ah2[i], bh, c2[i][j]);
+          c2[i][j] = mfma<F16>(ah2[i], bl, c2[i][j]);
+          c2[i][j] = mfma<F16>(al2[i], bh, c2[i][j]);
+        }
+      }
+    }
+  }
+
+  const long col0 = a.pcol[P] - a.col_base;
+  // sqrt(1/2) and sqrt(3/2) as float pairs: every column is multiplied with
+  // one rounding (fma), so the constants' own float rounding does not bias
+  // all P or all M columns alike
+  const float cp_hi = 0.707106769084930419921875f, cp_lo = 1.2101617485882343e-08f;
+  const float cm_hi = 1.22474491596221923828125f, cm_lo = -4.4570629853524224e-08f;
+  const double epq = a.ep[p] + a.ep[q];
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int c = c0 + 16 * j + fr;
+    if (c >= a.nc) continue;
+    const float wgt = (float)(epq - a.ec[c]);
+    // undo the operand scales of the two products (exact powers of two)
+    int e1 = 0, e2 = 0;
+    if constexpr (F16) {
+      e1 = a.eR[p] + a.eS[(long)q * a.sEp + (long)c * a.sEc] - 2 * EMAX;
+      e2 = a.eR[q] + a.eS[(long)p * a.sEp + (long)c * a.sEc] - 2 * EMAX;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + wr + 16 * i + crow(lane, r);
+        if (x >= a.N) continue;
+        const long o = (long)x * a.ldz + col0 + c;
+        const float x1 = F16 ? ldexpf(c1[i][j][r], e1) : c1[i][j][r];
+        u16 h, l;
+        if (diag) {
+          split<F16>(a.zscale * x1, h, l); a.Zh[o] = h; a.Zl[o] = l;
+          split<F16>(a.wscale * (wgt * x1), h, l); a.Wh[o] = h; a.Wl[o] = l;
+        } else {
+          const float x2 = F16 ? ldexpf(c2[i][j][r], e2) : c2[i][j][r];
+          const float sp = x1 + x2, sm = x1 - x2;
+          const float zp = fmaf(sp, cp_hi, sp * cp_lo);
+          const float zm = fmaf(sm, cm_hi, sm * cm_lo);
+          split<F16>(a.zscale * zp, h, l); a.Zh[o] = h; a.Zl[o] = l;
+          split<F16>(a.wscale * (wgt * zp), h, l); a.Wh[o] = h; a.Wl[o] = l;
+          const long om = o + a.nc;
+          split<F16>(a.zscale * zm, h, l); a.Zh[om] = h; a.Zl[om] = l;
+          split<F16>(a.wscale * (wgt * zm), h, l); a.Wh[om] = h; a.Wl[om] = l;
+        }
+      }
+  }
+}
+
+struct SyrkArgs {
+  const u16* Zh; const u16* Zl; const u16* Wh; const u16* Wl; long ldz;
+  int N; long K; long kper;
+  double u0scale, u1scale;   // 2^-2fZ, 2^-(fZ+fW)
+  double* part; long part_stride;
+};
+
+constexpr int TS = 64;   // SYRK output tile
+
+__device__ __forceinline__ void kahan_add(double& s, double& c, double v) {
+  const double y = v - c;
+  const double t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+template <bool F16>
+__global__ __launch_bounds__(NT) void syrk_split_kernel(SyrkArgs a) {
+  __shared__ u16x8 sX[4][TS][KVP];   // Z hi, Z lo, wZ hi, wZ lo (x rows)
+  __shared__ u16x8 sY[2][TS][KVP];   // Z hi, Z lo (y rows)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t = blockIdx.x;
+  int xt = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((xt + 1) * (xt + 2) / 2 <= t) ++xt;
+  while (xt * (xt + 1) / 2 > t) --xt;
+  const int yt = t - xt * (xt + 1) / 2;
+  const int s = blockIdx.y;
+  const long k0 = (long)s * a.kper, k1 = std::min(a.K, k0 + a.kper);
+  if (k1 <= k0) return;
+  const int x0 = xt * TS, y0 = yt * TS;
+  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  u16x8 rx[4], ry[2];
+  auto load = [&](long kb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + NT * i;
+      const int arr = idx / (TS * KV), rr = (idx / KV) % TS, kv = idx % KV;
+      const int x = x0 + rr;
+      const long k = kb + 8 * kv;
+      const u16* base = arr == 0 ? a.Zh : arr == 1 ? a.Zl : arr == 2 ? a.Wh : a.Wl;
+      rx[i] = (x < a.N && k < k1) ? *reinterpret_cast<const u16x8*>(base + (long)x * a.ldz + k)
+                                  : zero8;
+      if (k < k1 && k + 8 > k1)   // vector straddles the end of the chunk
+        for (int e = 0; e < 8; ++e)
+          if (k + e >= k1) rx[i][e] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + NT * i;
+      const int arr = idx / (TS * KV), rr = (idx / KV) % TS, kv = idx % KV;
+      const int y = y0 + rr;
+      const long k = kb + 8 * kv;
+      const u16* base = arr == 0 ? a.Zh : a.Zl;
+      ry[i] = (y < a.N && k < k1) ? *reinterpret_cast<const u16x8*>(base + (long)y * a.ldz + k)
+                                  : zero8;
+      if (k < k1 && k + 8 > k1)
+        for (int e = 0; e < 8; ++e)
+          if (k + e >= k1) ry[i][e] = 0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + NT * i;
+      sX[idx / (TS * KV)][(idx / KV) % TS][idx % KV] = rx[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + NT * i;
+      sY[idx / (TS * KV)][(idx / KV) % TS][idx % KV] = ry[i];
+    }
+  };
+
+  const int fr = lane & 15, fk = lane >> 4;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  // hi*hi products and the ~2^-11 smaller cross products (hi*lo, lo*hi,
+  // lo*lo) accumulate separately, so the large sum is rounded once per step
+  f4 u0[2][2], u1[2][2], v0[2][2], v1[2][2];
+  double s0[2][2][4], e0[2][2][4], s1[2][2][4], e1[2][2][4];
+  const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      u0[i][j] = u1[i][j] = v0[i][j] = v1[i][j] = z4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s0[i][j][r] = e0[i][j][r] = s1[i][j][r] = e1[i][j][r] = 0.0;
+    }
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          kahan_add(s0[i][j][r], e0[i][j][r],
+                    a.u0scale * ((double)u0[i][j][r] + (double)v0[i][j][r]));
+          kahan_add(s1[i][j][r], e1[i][j][r],
+                    a.u1scale * ((double)u1[i][j][r] + (double)v1[i][j][r]));
+        }
+        u0[i][j] = u1[i][j] = v0[i][j] = v1[i][j] = z4;
+      }
+  };
+
+  const long nsteps = (k1 - k0 + KS - 1) / KS;
+  load(k0);
+  for (long step = 0; step < nsteps; ++step) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (step + 1 < nsteps) load(k0 + (step + 1) * KS);
+    u16x8 xh[2], xl[2], wh[2], wl[2], yh[2], yl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      xh[i] = sX[0][wm + 16 * i + fr][fk];
+      xl[i] = sX[1][wm + 16 * i + fr][fk];
+      wh[i] = sX[2][wm + 16 * i + fr][fk];
+      wl[i] = sX[3][wm + 16 * i + fr][fk];
+      yh[i] = sY[0][wn + 16 * i + fr][fk];
+      yl[i] = sY[1][wn + 16 * i + fr][fk];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        u0[i][j] = mfma<F16>(xh[i], yh[j], u0[i][j]);
+        v0[i][j] = mfma<F16>(xh[i], yl[j], v0[i][j]);
+        v0[i][j] = mfma<F16>(xl[i], yh[j], v0[i][j]);
+        v0[i][j] = mfma<F16>(xl[i], yl[j], v0[i][j]);
+        u1[i][j] = mfma<F16>(wh[i], yh[j], u1[i][j]);
+        v1[i][j] = mfma<F16>(wh[i], yl[j], v1[i][j]);
+        v1[i][j] = mfma<F16>(wl[i], yh[j], v1[i][j]);
+        v1[i][j] = mfma<F16>(wl[i], yl[j], v1[i][j]);
+      }
+    if ((step + 1) % KC_STEPS == 0) flush();
+  }
+  flush();
+
+  double* P0 = a.part + (long)s * a.part_stride;
+  double* P1 = P0 + (long)a.N * a.N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + wm + 16 * i + crow(lane, r);
+        const int y = y0 + wn + 16 * j + fr;
+        if (x >= a.N || y >= a.N) continue;
+        const long o = (long)x * a.N + y;
+        P0[o] += s0[i][j][r] - e0[i][j][r];
+        P1[o] += s1[i][j][r] - e1[i][j][r];
+      }
+}
+
+struct PairTable {
+  std::vector<int> pi, pj;
+  std::vector<long> col;
+};
+
+PairTable make_pairs(int np, int nc) {
+  PairTable t;
+  long c = 0;
+  for (int p = 0; p < np; ++p)
+    for (int q = p; q < np; ++q) {
+      t.pi.push_back(p); t.pj.push_back(q); t.col.push_back(c);
+      c += (p == q) ? nc : 2L * nc;
+    }
+  t.col.push_back(c);
+  return t;
+}
+
+int pick_cb(int nc) {
+  const int cands[4] = {8, 6, 5, 4};
+  int best = 4;
+  long best_cols = -1;
+  for (int cb : cands) {
+    const long w = 16L * cb;
+    const long cols = (nc + w - 1) / w * w;
+    if (best_cols < 0 || cols < best_cols) { best_cols = cols; best = cb; }
+  }
+  return best;
+}
+
+template <bool F16>
+void launch_slab(int cb, long G, hipStream_t st, const SlabArgs& sa) {
+  switch (cb) {
+    case 4: hipLaunchKernelGGL((slab_split_kernel<4, F16>), dim3((unsigned)G), dim3(NT), 0, st, sa); break;
+    case 5: hipLaunchKernelGGL((slab_split_kernel<5, F16>), dim3((unsigned)G), dim3(NT), 0, st, sa); break;
+    case 6: hipLaunchKernelGGL((slab_split_kernel<6, F16>), dim3((unsigned)G), dim3(NT), 0, st, sa); break;
+    default: hipLaunchKernelGGL((slab_split_kernel<8, F16>), dim3((unsigned)G), dim3(NT), 0, st, sa); break;
+  }
+  AGF2_CHECK_LAUNCH();
+}
+
+template <bool F16>
+void split_rows(const double* in, long s_in_a, long s_in_b, int na, int nb, const int* perm,
+                u16* hi, u16* lo, long s_out_a, long s_out_b, int Qs, const int* gexp, long gsa,
+                long gsb, hipStream_t st) {
+  const long rows = (long)na * nb;
+  const long tot = rows * Qs;
+  if (tot == 0) return;
+  const long blocks = std::min<long>((tot + 255) / 256, 16384);
+  hipLaunchKernelGGL((split_rows_kernel<F16>), dim3(blocks), dim3(256), 0, st, in, s_in_a,
+                     s_in_b, nb, perm, hi, lo, s_out_a, s_out_b, Qs, rows, gexp, gsa, gsb);
+  AGF2_CHECK_LAUNCH();
+}
+
+// sq[Q] = sum_pq L[Q][p][q]^2 (one workgroup per Q)
+__global__ __launch_bounds__(256) void slice_norm_kernel(const double* L, long nn, double* sq) {
+  __shared__ double red[256];
+  const double* LQ = L + blockIdx.x * nn;
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < nn; i += 256) acc += LQ[i] * LQ[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sq[blockIdx.x] = red[0];
+}
+
+void row_stats(const double* in, long s_in_a, long s_in_b, int na, int nb, int Q, long gsa,
+               long gsb, int* gexp, unsigned long long* nrm2, hipStream_t st) {
+  const long rows = (long)na * nb;
+  if (rows == 0) return;
+  const long blocks = std::min<long>((rows + 3) / 4, 8192);
+  hipLaunchKernelGGL(row_stats_kernel, dim3(blocks), dim3(256), 0, st, in, s_in_a, s_in_b, nb,
+                     Q, rows, gsa, gsb, gexp, nrm2);
+  AGF2_CHECK_LAUNCH();
+}
+
+// binary exponent e with |x| < 2^e (x > 0)
+int exponent_above(double x) {
+  int e = 0;
+  if (x > 0.0) std::frexp(x, &e);
+  return e;
+}
+
+struct PartScales {
+  const int* eR = nullptr;
+  const int* eS = nullptr;
+  long sEp = 0, sEc = 0;
+  float zscale = 1.f, wscale = 1.f;
+  double u0scale = 1.0, u1scale = 1.0;
+};
+
+}  // namespace
+
+template <bool F16>
+static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, const u16* Rl,
+                               long sRp, long sRx, const u16* Sh, const u16* Sl, long sSp,
+                               long sSc, const double* ep, int np, const double* ec, int nc,
+                               const PartScales& sc, double* U0, double* U1) {
+  hipStream_t st = h.stream;
+  const long nn = (long)N * N;
+  if (np == 0 || nc == 0) {
+    AGF2_HIP(hipMemsetAsync(U0, 0, nn * sizeof(double), st));
+    AGF2_HIP(hipMemsetAsync(U1, 0, nn * sizeof(double), st));
+    return;
+  }
+  PairTable t = make_pairs(np, nc);
+  const int npairs = (int)t.pi.size();
+  int* d_pi = h.ws_moments[6].as<int>(2L * npairs);
+  int* d_pj = d_pi + npairs;
+  long* d_col = h.ws_moments[7].as<long>(npairs + 1);
+  AGF2_HIP(hipMemcpyAsync(d_pi, t.pi.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
+  AGF2_HIP(hipMemcpyAsync(d_pj, t.pj.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
+  AGF2_HIP(hipMemcpyAsync(d_col, t.col.data(), (npairs + 1) * sizeof(long),
+                          hipMemcpyHostToDevice, st));
+  AGF2_HIP(hipStreamSynchronize(st));   // host tables go out of scope below
+
+  const long cap_bytes = 512L << 20;   // Z chunk: 4 arrays of 16-bit values
+  long kcap = std::max<long>(2L * nc, cap_bytes / (8L * N));
+  kcap = std::min<long>(kcap, t.col.back());
+  kcap = (kcap + KS - 1) / KS * KS;
+  u16* Z = h.ws_moments[4].as<u16>(4L * N * kcap);
+  u16 *Zh = Z, *Zl = Z + (long)N * kcap, *Wh = Z + 2L * N * kcap, *Wl = Z + 3L * N * kcap;
+
+  const int tiles_n = (N + TS - 1) / TS;
+  const int nlower = tiles_n * (tiles_n + 1) / 2;
+  const int nsplit_max = std::max(1, std::min(64, (2048 + nlower - 1) / nlower));
+  const long part_stride = 2 * nn;
+  double* part = h.ws_moments[5].as<double>(part_stride * nsplit_max);
+  AGF2_HIP(hipMemsetAsync(part, 0, part_stride * nsplit_max * sizeof(double), st));
+
+  const int cb = pick_cb(nc);
+  const int tiles_x = (N + TX - 1) / TX, tiles_c = (nc + 16 * cb - 1) / (16 * cb);
+  int P0 = 0;
+  while (P0 < npairs) {
+    int P1 = P0;
+    while (P1 < npairs && t.col[P1 + 1] - t.col[P0] <= kcap) ++P1;
+    if (P1 == P0) P1 = P0 + 1;
+    const long Kc = t.col[P1] - t.col[P0];
+    SlabArgs sa;
+    sa.Rh = Rh; sa.Rl = Rl; sa.sRp = sRp; sa.sRx = sRx;
+    sa.Sh = Sh; sa.Sl = Sl; sa.sSp = sSp; sa.sSc = sSc;
+    sa.eR = sc.eR; sa.eS = sc.eS; sa.sEp = sc.sEp; sa.sEc = sc.sEc;
+    sa.zscale = sc.zscale; sa.wscale = sc.wscale;
+    sa.ep = ep; sa.ec = ec; sa.N = N; sa.nc = nc; sa.Qs = Qs;
+    sa.pi = d_pi; sa.pj = d_pj; sa.pcol = d_col;
+    sa.pair0 = P0; sa.npairs = P1 - P0; sa.col_base = t.col[P0];
+    sa.Zh = Zh; sa.Zl = Zl; sa.Wh = Wh; sa.Wl = Wl; sa.ldz = kcap;
+    sa.tiles_x = tiles_x; sa.tiles_c = tiles_c;
+    long nd = 0;
+    for (int P = P0; P < P1; ++P) nd += (t.pi[P] == t.pj[P]);
+    const double slabs = 2.0 * (P1 - P0) - (double)nd;
+    {
+      ProfScope ps(h, "moments.slab", slabs * 2.0 * N * nc * Q, 8.0 * (N + 0.0) * Kc);
+      launch_slab<F16>(cb, (long)sa.npairs * tiles_x * tiles_c, st, sa);
+    }
+    int nsplit = (int)std::min<long>(nsplit_max, std::max<long>(1, Kc / 1024));
+    long kper = (Kc + nsplit - 1) / nsplit;
+    kper = (kper + KS - 1) / KS * KS;
+    nsplit = (int)((Kc + kper - 1) / kper);
+    SyrkArgs ya;
+    ya.Zh = Zh; ya.Zl = Zl; ya.Wh = Wh; ya.Wl = Wl; ya.ldz = kcap;
+    ya.N = N; ya.K = Kc; ya.kper = kper;
+    ya.u0scale = sc.u0scale; ya.u1scale = sc.u1scale;
+    ya.part = part; ya.part_stride = part_stride;
+    {
+      ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 0.0) * Kc);
+      hipLaunchKernelGGL((syrk_split_kernel<F16>), dim3(nlower, nsplit), dim3(NT), 0, st, ya);
+      AGF2_CHECK_LAUNCH();
+    }
+    P0 = P1;
+  }
+  ProfScope ps(h, "moments.reduce", 0.0, 8.0 * (2.0 * nsplit_max + 2.0) * nn);
+  reduce_moment_partials(part, part_stride, nsplit_max, N, U0, U1, st);
+}
+
+template <bool F16>
+static void build_split(Handle& h, int N, int Q, const double* L, int npole, int nocc,
+                        const double* e, const double* u, double* m0o, double* m1o,
+                        double* m0v, double* m1v) {
+  hipStream_t st = h.stream;
+  const int o = nocc, v = npole - nocc;
+  const int Qp = (Q + 15) / 16 * 16;   // float64 staging (transform) padding
+  const int Qs = (Q + KS - 1) / KS * KS;
+  u16* Sxo = h.ws_moments[0].as<u16>(2L * o * N * Qs);
+  u16* Sxv = h.ws_moments[1].as<u16>(2L * v * N * Qs);
+  u16* Sov = h.ws_moments[2].as<u16>(2L * o * v * Qs);
+  u16 *Rxo_h = Sxo, *Rxo_l = Sxo + (long)o * N * Qs;
+  u16 *Rxv_h = Sxv, *Rxv_l = Sxv + (long)v * N * Qs;
+  u16 *Rov_h = Sov, *Rov_l = Sov + (long)o * v * Qs;
+  // fp16 scale exponents: per occupied pole, per virtual pole, per (i, a) row;
+  // then the squared-norm maxima of the three tensors' Q rows
+  int* ex = h.ws_misc[7].as<int>((long)npole + (long)o * v + 8);
+  int* eRo = ex;
+  int* eRv = ex + o;
+  int* eOV = ex + npole;
+  unsigned long long* nrm = reinterpret_cast<unsigned long long*>(
+      h.ws_red.as<double>(4096) + 4000);   // 3 slots
+  if (F16) {
+    AGF2_HIP(hipMemsetAsync(ex, 0x80, ((long)npole + (long)o * v) * sizeof(int), st));
+    AGF2_HIP(hipMemsetAsync(nrm, 0, 3 * sizeof(unsigned long long), st));
+  }
+  // Summation order of the Q index: ascending Frobenius norm of the DF
+  // slices, so float32 accumulation adds small contributions before large
+  // ones (a relabelling of the summed index; the result is unchanged in exact
+  // arithmetic).
+  int* perm = h.ws_misc[6].as<int>(Qs);
+  {
+    double* sq = h.ws_misc[5].as<double>(Q);
+    hipLaunchKernelGGL(slice_norm_kernel, dim3(Q), dim3(256), 0, st, L, (long)N * N, sq);
+    AGF2_CHECK_LAUNCH();
+    std::vector<double> hsq(Q);
+    AGF2_HIP(hipMemcpyAsync(hsq.data(), sq, Q * sizeof(double), hipMemcpyDeviceToHost, st));
+    AGF2_HIP(hipStreamSynchronize(st));
+    std::vector<int> hp(Qs, -1);
+    std::vector<int> idx(Q);
+    for (int q = 0; q < Q; ++q) idx[q] = q;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return hsq[a] < hsq[b]; });
+    // padding first (zeros), then ascending slices
+    for (int q = 0; q < Q; ++q) hp[Qs - Q + q] = idx[q];
+    AGF2_HIP(hipMemcpyAsync(perm, hp.data(), Qs * sizeof(int), hipMemcpyHostToDevice, st));
+    AGF2_HIP(hipStreamSynchronize(st));
+  }
+  {
+    ProfScope ps(h, "moments.transform",
+                 2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
+                 8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
+    // float64 staging in chunks of poles (<= ~1 GiB each)
+    const long per_pole = (long)N * Qp;
+    const int pc = (int)std::max<long>(1, std::min<long>(npole, (1L << 27) / per_pole));
+    double* T = h.ws_moments[3].as<double>((long)pc * per_pole + (long)o * pc * Qp);
+    double* Tov = T + (long)pc * per_pole;
+    for (int p0 = 0; p0 < o; p0 += pc) {
+      const int np = std::min(pc, o - p0);
+      pole_transform_f64(h, N, Q, Qp, L, u, npole, p0, np, T);
+      // rows (p, x); one exponent per pole p
+      if (F16) row_stats(T, per_pole, Qp, np, N, Q, 1, 0, eRo + p0, nrm + 0, st);
+      split_rows<F16>(T, per_pole, Qp, np, N, perm, Rxo_h + (long)p0 * N * Qs,
+                      Rxo_l + (long)p0 * N * Qs, (long)N * Qs, Qs, Qs,
+                      F16 ? eRo + p0 : nullptr, 1, 0, st);
+    }
+    for (int a0 = 0; a0 < v; a0 += pc) {
+      const int na = std::min(pc, v - a0);
+      pole_transform_f64(h, N, Q, Qp, L, u, npole, o + a0, na, T);
+      if (F16) row_stats(T, per_pole, Qp, na, N, Q, 1, 0, eRv + a0, nrm + 1, st);
+      split_rows<F16>(T, per_pole, Qp, na, N, perm, Rxv_h + (long)a0 * N * Qs,
+                      Rxv_l + (long)a0 * N * Qs, (long)N * Qs, Qs, Qs,
+                      F16 ? eRv + a0 : nullptr, 1, 0, st);
+      // Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q] for this chunk of a
+      Gemm g;
+      g.M = o; g.N = Q; g.K = N; g.batch = na;
+      g.A = u; g.sAm = 1; g.sAk = npole;
+      g.B = T; g.sBb = per_pole; g.sBk = Qp; g.sBn = 1;
+      g.C = Tov; g.sCb = Qp; g.sCm = (long)na * Qp; g.sCn = 1;
+      gemm_f64_padded(g, Qp, st);
+      // rows (i, a); one exponent per row, stored at i * v + a
+      if (F16) row_stats(Tov, (long)na * Qp, Qp, o, na, Q, v, 1, eOV + a0, nrm + 2, st);
+      split_rows<F16>(Tov, (long)na * Qp, Qp, o, na, perm, Rov_h + (long)a0 * Qs,
+                      Rov_l + (long)a0 * Qs, (long)v * Qs, Qs, Qs, F16 ? eOV + a0 : nullptr,
+                      v, 1, st);
+    }
+  }
+  PartScales lesser, greater;
+  if (F16) {
+    // Cauchy-Schwarz: |(xp|qc)| <= |R[p][x]| |S[q][c]| (Q-space norms), so
+    // |Z|, |wZ| <= sqrt(6) * max|R| max|S| (* max|w|)
+    unsigned long long hn[3];
+    AGF2_HIP(hipMemcpyAsync(hn, nrm, sizeof hn, hipMemcpyDeviceToHost, st));
+    std::vector<double> he(npole);
+    AGF2_HIP(hipMemcpyAsync(he.data(), e, npole * sizeof(double), hipMemcpyDeviceToHost, st));
+    AGF2_HIP(hipStreamSynchronize(st));
+    double n2[3];
+    for (int k = 0; k < 3; ++k) std::memcpy(&n2[k], &hn[k], sizeof(double));
+    double eo_max = 0.0, ev_max = 0.0;
+    for (int i = 0; i < o; ++i) eo_max = std::max(eo_max, std::fabs(he[i]));
+    for (int a = o; a < npole; ++a) ev_max = std::max(ev_max, std::fabs(he[a]));
+    auto make = [&](const int* eR, double nR2, double wmax, long sEp, long sEc) {
+      PartScales sc;
+      sc.eR = eR; sc.eS = eOV; sc.sEp = sEp; sc.sEc = sEc;
+      const double zb = std::sqrt(6.0 * nR2 * n2[2]);
+      const double wb = zb * wmax;
+      const int fZ = EMAX - exponent_above(zb), fW = EMAX - exponent_above(wb);
+      sc.zscale = std::ldexp(1.0f, fZ);
+      sc.wscale = std::ldexp(1.0f, fW);
+      sc.u0scale = std::ldexp(1.0, -2 * fZ);
+      sc.u1scale = std::ldexp(1.0, -fZ - fW);
+      return sc;
+    };
+    lesser = make(eRo, n2[0], 2.0 * eo_max + ev_max, (long)v, 1L);
+    greater = make(eRv, n2[1], 2.0 * ev_max + eo_max, 1L, (long)v);
+  }
+  moments_part_split<F16>(h, N, Q, Qs, Rxo_h, Rxo_l, (long)N * Qs, Qs, Rov_h, Rov_l,
+                          (long)v * Qs, Qs, e, o, e + o, v, lesser, m0o, m1o);
+  moments_part_split<F16>(h, N, Q, Qs, Rxv_h, Rxv_l, (long)N * Qs, Qs, Rov_h, Rov_l, Qs,
+                          (long)v * Qs, e + o, v, e, o, greater, m0v, m1v);
+}
+
 void build_moments_split(Handle& h, int N, int Q, const double* L, int npole, int nocc,
                          const double* e, const double* u, double* m0o, double* m1o,
-                         double* m0v, double* m1v) {
-  (void)h; (void)N; (void)Q; (void)L; (void)npole; (void)nocc; (void)e; (void)u;
-  (void)m0o; (void)m1o; (void)m0v; (void)m1v;
-  throw Error{AGF2_ERR_ARG, "AGF2_SPLIT_BF16 is not available in this build"};
+                         double* m0v, double* m1v, bool fp16) {
+  if (fp16)
+    build_split<true>(h, N, Q, L, npole, nocc, e, u, m0o, m1o, m0v, m1v);
+  else
+    build_split<false>(h, N, Q, L, npole, nocc, e, u, m0o, m1o, m0v, m1v);
 }
 
 }  // namespace agf2

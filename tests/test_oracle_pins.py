@@ -347,3 +347,16 @@ def test_partial_pole_sums_add_up():
     b = O.se_moments(L, e, u, 10, occ_sel=[1, 2, 4, 5, 6, 8, 9], vir_sel=list(range(1, 17, 2)))
     for f, x, y in zip(full, a, b):
         assert rel(x + y, f) < 1e-14
+
+
+def test_sampled_elements_equal_full_moments():
+    """The per-element route used to sample large systems gives the same
+    numbers as the full build (different contraction order)."""
+    eps, L, nocc = small_system(nmo=11, nocc=3, naux=25)
+    e, u = syn.random_poles(6, 11, 30, 12)
+    full = O.se_moments(L, e, u, 12)
+    pairs = [(0, 0), (3, 7), (10, 2), (5, 5)]
+    el = O.se_moment_elements(L, e, u, 12, pairs)
+    for k, (p, q) in enumerate(pairs):
+        for m in range(4):
+            assert abs(el[k, m] - full[m][p, q]) < 1e-13 * np.abs(full[m]).max()
