@@ -54,32 +54,39 @@ def blas_threads():
         return os.cpu_count()
 
 
-def cpu_baseline(L, eps, nocc, n_occ_sample, n_vir_sample):
+def cpu_baseline(L, eps, nocc, n_occ_sample, n_vir_sample, log):
     """The oracle's moment build on a bounded sample of the same workload:
     the full pole-basis transform plus the contributions of a few outer
-    summed poles, extrapolated linearly in the number of outer poles."""
+    summed poles, extrapolated linearly in the number of outer poles (the
+    build is a sum of independent per-pole contributions)."""
     from oracle import agf2_oracle as O
     N = eps.shape[0]
     u = np.eye(N)
     o, v = nocc, N - nocc
     t0 = time.perf_counter()
-    O.pole_basis_df(L, u, nocc)
+    T = O.pole_basis_df(L, u, nocc)
     t_tr = time.perf_counter() - t0
+    log(f"oracle transform {t_tr:.1f}s")
     occ_sel = list(range(0, o, max(1, o // n_occ_sample)))[:n_occ_sample]
     vir_sel = list(range(0, v, max(1, v // n_vir_sample)))[:n_vir_sample]
     t0 = time.perf_counter()
-    O.se_moments(L, eps, u, nocc, occ_sel=occ_sel, vir_sel=[])
+    O.se_moments(L, eps, u, nocc, occ_sel=occ_sel, vir_sel=[], tensors=T)
     t_o = time.perf_counter() - t0
+    log(f"oracle {len(occ_sel)} occupied poles {t_o:.1f}s")
     t0 = time.perf_counter()
-    O.se_moments(L, eps, u, nocc, occ_sel=[], vir_sel=vir_sel)
+    O.se_moments(L, eps, u, nocc, occ_sel=[], vir_sel=vir_sel, tensors=T)
     t_v = time.perf_counter() - t0
-    # each partial call repeats the transform: remove it once per call
-    per_i = max(t_o - t_tr, 0.0) / len(occ_sel)
-    per_a = max(t_v - t_tr, 0.0) / len(vir_sel)
+    log(f"oracle {len(vir_sel)} virtual poles {t_v:.1f}s")
+    per_i = t_o / len(occ_sel)
+    per_a = t_v / len(vir_sel)
     t_full = t_tr + o * per_i + v * per_a
     return t_full, dict(t_transform=t_tr, per_occ_pole=per_i, per_vir_pole=per_a,
                         occ_sample=len(occ_sel), vir_sample=len(vir_sel),
                         measured_s=t_tr + t_o + t_v)
+
+
+def log(msg):
+    print(f"# {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -88,11 +95,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "split_bf16", "split_fp16"])
+    ap.add_argument("--prec", default="split_fp16", choices=["fp64", "split_bf16", "split_fp16"])
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-occ-sample", type=int, default=1)
-    ap.add_argument("--cpu-vir-sample", type=int, default=2)
+    ap.add_argument("--cpu-vir-sample", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -107,8 +114,7 @@ def main():
     seed = SEEDS[args.workload] if args.seed is None else args.seed
     t0 = time.perf_counter()
     eps, L = generate(seed, N, nocc, Q)
-    print(f"# generated nmo={N} nocc={nocc} naux={Q} in {time.perf_counter() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    log(f"generated nmo={N} nocc={nocc} naux={Q} in {time.perf_counter() - t0:.1f}s")
 
     dev = torch.device("cuda", 0)
     Ld = torch.from_numpy(L).to(dev)
@@ -118,6 +124,8 @@ def main():
     D0[:nocc, :nocc] = 2.0 * torch.eye(nocc, dtype=torch.float64, device=dev)
     h = agf2.Handle(0)
     hcore = agf2.agf2_fock_build(h, Ld, torch.diag(epsd).contiguous(), D0, -1.0)
+    torch.cuda.synchronize()
+    log("inputs resident on the GPU")
     m_out = tuple(h.empty(N, N) for _ in range(4))
     o, v = nocc, N - nocc
     F_canon = canonical_flops(N, o, v, Q)
@@ -128,12 +136,15 @@ def main():
         ev0.record()
         m = agf2.agf2_build_moments(h, Ld, epsd, eye, nocc, prec=args.prec, out=m_out)
         ev1.record()
+        ev1.synchronize()
+        log(f"moments built ({ev0.elapsed_time(ev1) / 1e3:.2f}s)")
         no, eo, vo = agf2.agf2_compress(h, m[0], m[1])
         nv, evv, vv = agf2.agf2_compress(h, m[2], m[3])
         e_se = torch.cat([eo[:no], evv[:nv]]).contiguous()
         v_se = torch.cat([vo[:, :no], vv[:, :nv]], dim=1).contiguous()
         D = D0.clone()
         fl = agf2.agf2_fock_loop(h, Ld, hcore, 2 * nocc, e_se, v_se, D)
+        log(f"Fock loop done ({fl['n_cycle']} cycles)")
         e1, e2 = agf2.agf2_energy_gf(h, hcore, fl["fock"], D, fl["e_pole"], fl["u_pole"],
                                      fl["nocc_pole"], e_se[:no].contiguous(),
                                      vo[:, :no].contiguous(), e_se[no:].contiguous(),
@@ -196,7 +207,9 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        t_full, info = cpu_baseline(L, eps, nocc, args.cpu_occ_sample, args.cpu_vir_sample)
+        log("timing the oracle on a sample")
+        t_full, info = cpu_baseline(L, eps, nocc, args.cpu_occ_sample, args.cpu_vir_sample,
+                                    log)
         out["cpu_baseline"] = {
             "value": round(F_canon / t_full / 1e12, 6), "unit": "TFLOP/s",
             "cores": blas_threads(),

@@ -207,6 +207,61 @@ agf2_status agf2_energy_gf(agf2_handle_t handle, int nphys,
                            const double* e_se_vir, const double* v_se_vir,
                            double* e_1b, double* e_2b);
 
+/* Options of the outer self-consistent loop. */
+typedef struct {
+  int max_iter;           /* iterations after iteration 0                    */
+  double conv_tol;        /* |change of the total energy|, Ha                */
+  double conv_tol_ipea;   /* max |change of IP|, |change of EA|, Ha          */
+  int diis_space;         /* DIIS vectors on the four moments (0 = off)      */
+  double damping;         /* m <- (1 - damping) m + damping m_prev           */
+  agf2_precision prec;    /* arithmetic of the moment build                  */
+  double compress_tol;    /* see agf2_compress                               */
+  agf2_fock_opts fock;    /* Fock-loop options                               */
+} agf2_run_opts;
+
+/* Defaults: max_iter 20, conv_tol 1e-8, conv_tol_ipea 1e-7, diis_space 8,
+ * damping 0, prec AGF2_FP64, compress_tol 0, fock as agf2_fock_opts_default. */
+void agf2_run_opts_default(agf2_run_opts* opts);
+
+/* One record per iteration of agf2_run. */
+typedef struct {
+  int iter;                      /* 0 = built from the mean-field poles    */
+  int nocc_pole, npole, fock_cycles, warm;
+  double e_1b, e_2b, e_tot;      /* Ha                                     */
+  double ip, ea, w_ip, w_ea;     /* IP = -(highest occupied pole), EA,
+                                    and their quasiparticle weights        */
+  double mu, shift;              /* chemical potential, auxiliary shift    */
+  double t_moments, t_compress, t_fock, t_energy;   /* seconds            */
+} agf2_iter_record;
+
+/*
+ * AGF2(1,0) to self-consistency (the method as reviewed in the paper):
+ * iteration 0 builds the moments from the mean-field poles (energies e_mf,
+ * amplitudes = identity, the first nocc occupied); every iteration then
+ * extrapolates the moments (DIIS, damping), compresses the lesser and greater
+ * parts to nphys auxiliaries each, relaxes the density in the Fock loop
+ * (starting from the previous density; 2 * diag(1_occ) at first), evaluates
+ * the Galitskii-Migdal energy and IP/EA, and builds the next moments from the
+ * nphys + 2 nphys poles. Converged when |dE| < conv_tol and max(|dIP|,
+ * |dEA|) < conv_tol_ipea.
+ *   Lpq device [naux][nphys][nphys]; hcore device [nphys][nphys];
+ *   e_mf device [nphys]; nocc doubly occupied orbitals (nelec = 2 nocc).
+ *   dm_init    device [4][nphys][nphys] or NULL: a correction added to the
+ *              iteration-0 moments (warm start); if the corrected moments
+ *              cannot be compressed, iteration 0 is redone without it
+ *              (record.warm says which was used).
+ *   records    host [max_iter + 1] outputs; n_records, converged host.
+ *   e_pole [3 nphys], u_pole [nphys][3 nphys], rdm1 [nphys][nphys] device
+ *   outputs (the final Green's function and density); nocc_pole host.
+ * Returns AGF2_ERR_NO_CONVERGE when max_iter is reached (outputs valid).
+ */
+agf2_status agf2_run(agf2_handle_t handle, const agf2_run_opts* opts,
+                     int nphys, int naux, const double* Lpq,
+                     const double* hcore, const double* e_mf, int nocc,
+                     const double* dm_init, agf2_iter_record* records,
+                     int* n_records, int* converged, double* e_pole,
+                     double* u_pole, int* nocc_pole, double* rdm1);
+
 /*
  * Kernel timing (tracing aid, not part of the method). When enabled, the
  * library records hipEvents on its stream around every launch of each

@@ -72,15 +72,19 @@ def reference_density(nmo, nocc):
 def pole_basis_df(L, u_pole, nocc_pole):
     """DF tensors in the pole basis: Lxo[Q,x,i] = sum_r L[Q,x,r] u[r,i],
     Lxv[Q,x,a] likewise, Lov[Q,i,a] = sum_xr u[x,i] L[Q,x,r] u[r,a]."""
-    uo = u_pole[:, :nocc_pole]
-    uv = u_pole[:, nocc_pole:]
-    Lxo = np.einsum("Qxr,ri->Qxi", L, uo, optimize=True)
-    Lxv = np.einsum("Qxr,ra->Qxa", L, uv, optimize=True)
-    Lov = np.einsum("xi,Qxa->Qia", uo, Lxv, optimize=True)
+    Q, N, _ = L.shape
+    uo = np.ascontiguousarray(u_pole[:, :nocc_pole])
+    uv = np.ascontiguousarray(u_pole[:, nocc_pole:])
+    Lm = L.reshape(Q * N, N)
+    Lxo = (Lm @ uo).reshape(Q, N, -1)
+    Lxv = (Lm @ uv).reshape(Q, N, -1)
+    Lov = np.empty((Q, uo.shape[1], uv.shape[1]))
+    for q in range(Q):
+        Lov[q] = uo.T @ Lxv[q]
     return Lxo, Lxv, Lov
 
 
-def se_moments(L, e_pole, u_pole, nocc_pole, occ_sel=None, vir_sel=None):
+def se_moments(L, e_pole, u_pole, nocc_pole, occ_sel=None, vir_sel=None, tensors=None):
     """Zeroth and first moments of the lesser and greater second-order
     self-energy, built from the Green's function poles (e_pole, u_pole).
 
@@ -100,6 +104,8 @@ def se_moments(L, e_pole, u_pole, nocc_pole, occ_sel=None, vir_sel=None):
     from the DF factorisation. occ_sel / vir_sel restrict the outermost sum
     (over i for the lesser part, over a for the greater part) to a subset of
     poles; the full moments are the sums of these partial contributions.
+    tensors, if given, is the output of pole_basis_df for these poles (reused
+    instead of transforming again).
     Returns (U0<, U1<, U0>, U1>).
     """
     N = u_pole.shape[0]
@@ -107,7 +113,7 @@ def se_moments(L, e_pole, u_pole, nocc_pole, occ_sel=None, vir_sel=None):
     eo = e_pole[:nocc_pole]
     ev = e_pole[nocc_pole:]
     o, v = eo.shape[0], ev.shape[0]
-    Lxo, Lxv, Lov = pole_basis_df(L, u_pole, nocc_pole)
+    Lxo, Lxv, Lov = pole_basis_df(L, u_pole, nocc_pole) if tensors is None else tensors
     Lxo_m = np.ascontiguousarray(Lxo.reshape(Q, N * o))       # [Q, (x,j)]
     Lxv_m = np.ascontiguousarray(Lxv.reshape(Q, N * v))       # [Q, (x,b)]
     Lov_m = np.ascontiguousarray(Lov.reshape(Q, o * v))       # [Q, (j,a)]
@@ -115,16 +121,16 @@ def se_moments(L, e_pole, u_pole, nocc_pole, occ_sel=None, vir_sel=None):
     m0o = np.zeros((N, N)); m1o = np.zeros((N, N))
     m0v = np.zeros((N, N)); m1v = np.zeros((N, N))
     for i in (range(o) if occ_sel is None else occ_sel):
-        xija = (Lxo[:, :, i].T @ Lov_m).reshape(N, o, v)               # (xi|ja)
-        xjia = (Lxo_m.T @ Lov[:, i, :]).reshape(N, o, v)              # (xj|ia)
+        xija = (np.ascontiguousarray(Lxo[:, :, i].T) @ Lov_m).reshape(N, o, v)   # (xi|ja)
+        xjia = (Lxo_m.T @ np.ascontiguousarray(Lov[:, i, :])).reshape(N, o, v)   # (xj|ia)
         w = eo[i] + eo[:, None] - ev[None, :]
         a = xija.reshape(N, -1)
         t = (2.0 * xija - xjia).reshape(N, -1)
         m0o += a @ t.T
         m1o += (a * w.reshape(1, -1)) @ t.T
     for a_ in (range(v) if vir_sel is None else vir_sel):
-        xabi = (Lxv[:, :, a_].T @ Lvo_m).reshape(N, v, o)             # (xa|bi)
-        xbai = (Lxv_m.T @ Lov[:, :, a_]).reshape(N, v, o)             # (xb|ai)
+        xabi = (np.ascontiguousarray(Lxv[:, :, a_].T) @ Lvo_m).reshape(N, v, o)  # (xa|bi)
+        xbai = (Lxv_m.T @ np.ascontiguousarray(Lov[:, :, a_])).reshape(N, v, o)  # (xb|ai)
         w = ev[a_] + ev[:, None] - eo[None, :]
         a = xabi.reshape(N, -1)
         t = (2.0 * xabi - xbai).reshape(N, -1)

@@ -38,6 +38,18 @@ class FockOpts(ctypes.Structure):
                 ("max_cycle", _I), ("diis_space", _I)]
 
 
+class RunOpts(ctypes.Structure):
+    _fields_ = [("max_iter", _I), ("conv_tol", _D), ("conv_tol_ipea", _D), ("diis_space", _I),
+                ("damping", _D), ("prec", _I), ("compress_tol", _D), ("fock", FockOpts)]
+
+
+class IterRecord(ctypes.Structure):
+    _fields_ = [("iter", _I), ("nocc_pole", _I), ("npole", _I), ("fock_cycles", _I),
+                ("warm", _I), ("e_1b", _D), ("e_2b", _D), ("e_tot", _D), ("ip", _D),
+                ("ea", _D), ("w_ip", _D), ("w_ea", _D), ("mu", _D), ("shift", _D),
+                ("t_moments", _D), ("t_compress", _D), ("t_fock", _D), ("t_energy", _D)]
+
+
 SIGNATURES = {
     "agf2_create": (_I, [ctypes.POINTER(_P), _I, _P]),
     "agf2_destroy": (_I, [_P]),
@@ -51,6 +63,9 @@ SIGNATURES = {
                             _DP, _IP, ctypes.POINTER(FockOpts)]),
     "agf2_energy_gf": (_I, [_P, _I, _P, _P, _P, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P,
                             _DP, _DP]),
+    "agf2_run_opts_default": (None, [ctypes.POINTER(RunOpts)]),
+    "agf2_run": (_I, [_P, ctypes.POINTER(RunOpts), _I, _I, _P, _P, _P, _I, _P,
+                      ctypes.POINTER(IterRecord), _IP, _IP, _P, _P, _IP, _P]),
     "agf2_profile_enable": (_I, [_P, _I]),
     "agf2_profile_count": (_I, [_P]),
     "agf2_profile_get": (_I, [_P, _I, ctypes.POINTER(ctypes.c_char_p),
@@ -253,3 +268,46 @@ def agf2_profile_read(h: Handle) -> dict:
         out[name.value.decode()] = dict(launches=launches.value, ms=ms.value, flops=fl.value,
                                         bytes=by.value)
     return out
+
+
+def run_opts(**kw) -> RunOpts:
+    """agf2_run options: the library defaults, overridden by keyword (prec may
+    be a name such as "split_fp16"; fock_* keys set Fock-loop options)."""
+    o = RunOpts()
+    load_library().agf2_run_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "prec":
+            v = PRECISIONS[v] if isinstance(v, str) else int(v)
+        if k.startswith("fock_"):
+            setattr(o.fock, k[5:], v)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def agf2_run(h: Handle, L, hcore, e_mf, nocc: int, opts: RunOpts = None, dm_init=None,
+             raise_on_no_converge=False):
+    """AGF2 to self-consistency. Returns a dict with the per-iteration records
+    (list of dicts), converged flag, final e_pole, u_pole, nocc_pole and rdm1."""
+    naux, nphys, _ = L.shape
+    opts = run_opts() if opts is None else opts
+    recs = (IterRecord * (opts.max_iter + 1))()
+    nrec = ctypes.c_int(0)
+    conv = ctypes.c_int(0)
+    nocc_pole = ctypes.c_int(0)
+    e_pole = h.empty(3 * nphys)
+    u_pole = h.empty(nphys, 3 * nphys)
+    rdm1 = h.empty(nphys, nphys)
+    d = h.device
+    st = h.lib.agf2_run(h.h, ctypes.byref(opts), nphys, naux, _ptr(L, "L", d),
+                        _ptr(hcore, "hcore", d), _ptr(e_mf, "e_mf", d), int(nocc),
+                        None if dm_init is None else _ptr(dm_init, "dm_init", d), recs,
+                        ctypes.byref(nrec), ctypes.byref(conv), _ptr(e_pole, "e_pole", d),
+                        _ptr(u_pole, "u_pole", d), ctypes.byref(nocc_pole), _ptr(rdm1, "rdm1", d))
+    if st != 0 and (st != -5 or raise_on_no_converge):
+        h._check(st)
+    history = [{f: getattr(recs[i], f) for f, _ in IterRecord._fields_} for i in range(nrec.value)]
+    npole = history[-1]["npole"] if history else nphys
+    return dict(history=history, converged=bool(conv.value), e_pole=e_pole[:npole],
+                u_pole=u_pole.view(-1)[:nphys * npole].view(nphys, npole),
+                nocc_pole=nocc_pole.value, rdm1=rdm1)

@@ -86,6 +86,7 @@ Handle::~Handle() {
   for (auto& b : ws_moments) b.release();
   for (auto& b : ws_fock) b.release();
   for (auto& b : ws_misc) b.release();
+  for (auto& b : ws_run) b.release();
   ws_red.release();
   if (host_red) (void)hipHostFree(host_red);
   if (blas) rocblas_destroy_handle(blas);
@@ -532,6 +533,138 @@ struct Diis {
   }
 };
 
+
+FockLoopResult fock_loop_impl(Handle& h, int nphys, int naux, const double* Lpq,
+                              const double* hcore, int nelec, int naux_se, double* e_se,
+                              const double* v_se, double* rdm1, double* fock, double* e_pole,
+                              double* u_pole, const agf2_fock_opts& o) {
+  if (nelec <= 0 || nelec % 2 != 0 || nelec >= 2 * (nphys + naux_se))
+    throw Error{AGF2_ERR_NELEC, "nelec must be even and in (0, 2 * npole)"};
+  AGF2_REQUIRE(o.max_cycle >= 1 && o.tol_rdm1 > 0 && o.tol_nelec > 0 && o.bracket > 0 &&
+                   o.step0 > 0 && o.diis_space >= 0,
+               "bad Fock-loop options");
+  hipStream_t s = h.stream;
+  const int N = nphys;
+  const long nn = (long)N * N;
+  FockLoop fl(h, N, naux, naux_se, Lpq, e_se, v_se, (double)nelec);
+  double* F = h.ws_fock[6].as<double>(3 * nn);
+  double* Fn = F + nn;
+  double* Dn = Fn + nn;
+  Diis diis(h, nn, o.diis_space, h.ws_fock[7]);
+  fock_build(h, N, naux, Lpq, hcore, rdm1, 1.0, F);
+  double d = 0.0;
+  bool converged = false;
+  int cycle = 0;
+  Aufbau a;
+  for (cycle = 1; cycle <= o.max_cycle; ++cycle) {
+    d = fl.fit_shift(F, d, o);
+    if (!(fl.solved_shift == d && fl.solved_F == F)) fl.solve(F, d);
+    a = aufbau(fl.n, fl.hlam, fl.hw, (double)nelec);
+    // D = 2 sum_{l < n*} phi_l phi_l^T (physical block)
+    Gemm g;
+    g.M = N; g.N = N; g.K = a.n;
+    g.A = fl.H; g.sAm = 1; g.sAk = fl.n;
+    g.B = fl.H; g.sBn = 1; g.sBk = fl.n;
+    g.C = Dn; g.sCm = N; g.sCn = 1; g.alpha = 2.0;
+    if (a.n > 0) gemm_f64(g, s);
+    else AGF2_HIP(hipMemsetAsync(Dn, 0, nn * sizeof(double), s));
+    // RMS change of D
+    hipLaunchKernelGGL(sqdiff_kernel, dim3(nblk(nn)), dim3(256), 0, s, nn, Dn, rdm1, Fn);
+    AGF2_CHECK_LAUNCH();
+    const double err = std::sqrt(dot_f64(h, nn, Fn, Fn) / (double)nn);
+    AGF2_HIP(hipMemcpyAsync(rdm1, Dn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (err < o.tol_rdm1) { converged = true; break; }
+    fock_build(h, N, naux, Lpq, hcore, rdm1, 1.0, Fn);
+    // error vector F[D] - F, stored in Dn (free now)
+    hipLaunchKernelGGL(sqdiff_kernel, dim3(nblk(nn)), dim3(256), 0, s, nn, Fn, F, Dn);
+    AGF2_CHECK_LAUNCH();
+    diis.update(Fn, Dn);
+    AGF2_HIP(hipMemcpyAsync(F, Fn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  if (cycle > o.max_cycle) cycle = o.max_cycle;
+  AGF2_HIP(hipMemcpyAsync(fock, F, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+  AGF2_HIP(hipMemcpyAsync(e_pole, fl.lam, fl.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  extract_poles(N, fl.n, fl.H, u_pole, s);
+  if (naux_se > 0) {
+    hipLaunchKernelGGL(add_scalar_kernel, dim3(nblk(naux_se)), dim3(256), 0, s,
+                       (long)naux_se, d, e_se);
+    AGF2_CHECK_LAUNCH();
+  }
+  AGF2_HIP(hipStreamSynchronize(s));
+  FockLoopResult r;
+  r.nocc_pole = a.n;
+  r.mu = a.mu;
+  r.shift = d;
+  r.n_cycle = cycle;
+  r.converged = converged;
+  return r;
+}
+
+void energy_impl(Handle& h, int nphys, const double* hcore, const double* fock,
+                 const double* rdm1, int npole, int nocc_pole, const double* e_pole,
+                 const double* u_pole, int naux_occ, const double* e_se_occ,
+                 const double* v_se_occ, int naux_vir, const double* e_se_vir,
+                 const double* v_se_vir, double* e_1b, double* e_2b) {
+  hipStream_t s = h.stream;
+  const long nn = (long)nphys * nphys;
+  double* part = h.ws_red.as<double>(4096);
+  const int nb1 = nblk(nn);
+  hipLaunchKernelGGL(e1b_kernel, dim3(nb1), dim3(256), 0, s, nn, hcore, fock, rdm1, part);
+  AGF2_CHECK_LAUNCH();
+  const double e1 = reduce_partials(h, part, nb1);
+  double e2 = 0.0;
+  const int nv = npole - nocc_pole;
+  // occupied poles x greater auxiliaries
+  if (nocc_pole > 0 && naux_vir > 0) {
+    double* c = h.ws_misc[6].as<double>((long)nocc_pole * naux_vir);
+    Gemm g;
+    g.M = nocc_pole; g.N = naux_vir; g.K = nphys;
+    g.A = u_pole; g.sAm = 1; g.sAk = npole;
+    g.B = v_se_vir; g.sBn = 1; g.sBk = naux_vir;
+    g.C = c; g.sCm = naux_vir; g.sCn = 1;
+    gemm_f64(g, s);
+    const int nb = nblk((long)nocc_pole * naux_vir);
+    hipLaunchKernelGGL(gm_sum_kernel, dim3(nb), dim3(256), 0, s, nocc_pole, naux_vir, c,
+                       e_pole, e_se_vir, 1.0, part);
+    AGF2_CHECK_LAUNCH();
+    e2 += reduce_partials(h, part, nb);
+  }
+  // virtual poles x lesser auxiliaries: (u_l.v_k)^2 / (e_k - lam_l)
+  if (nv > 0 && naux_occ > 0) {
+    double* c = h.ws_misc[6].as<double>((long)nv * naux_occ);
+    Gemm g;
+    g.M = nv; g.N = naux_occ; g.K = nphys;
+    g.A = u_pole + nocc_pole; g.sAm = 1; g.sAk = npole;
+    g.B = v_se_occ; g.sBn = 1; g.sBk = naux_occ;
+    g.C = c; g.sCm = naux_occ; g.sCn = 1;
+    gemm_f64(g, s);
+    const int nb = nblk((long)nv * naux_occ);
+    hipLaunchKernelGGL(gm_sum_kernel, dim3(nb), dim3(256), 0, s, nv, naux_occ, c,
+                       e_pole + nocc_pole, e_se_occ, -1.0, part);
+    AGF2_CHECK_LAUNCH();
+    e2 += reduce_partials(h, part, nb);
+  }
+  *e_1b = e1;
+  *e_2b = e2;
+}
+
+void build_moments(Handle& h, agf2_precision prec, int N, int Q, const double* L, int npole,
+                   int nocc, const double* e, const double* u, double* m0o, double* m1o,
+                   double* m0v, double* m1v) {
+  if (prec == AGF2_FP64)
+    build_moments_f64(h, N, Q, L, npole, nocc, e, u, m0o, m1o, m0v, m1v);
+  else if (prec == AGF2_SPLIT_BF16 || prec == AGF2_SPLIT_FP16)
+    build_moments_split(h, N, Q, L, npole, nocc, e, u, m0o, m1o, m0v, m1v,
+                        prec == AGF2_SPLIT_FP16);
+  else
+    throw Error{AGF2_ERR_ARG, "unknown precision mode"};
+}
+
+int compress_part(Handle& h, int N, const double* m0, const double* m1, double tol,
+                  double* e_aux, double* v_aux) {
+  return compress_impl(h, N, m0, m1, tol, e_aux, v_aux);
+}
+
 }  // namespace agf2
 
 using namespace agf2;
@@ -638,14 +771,8 @@ agf2_status agf2_build_moments(agf2_handle_t hh, agf2_precision prec, int nphys,
                  "need 1 <= nocc_pole < npole");
     AGF2_REQUIRE(Lpq && e_pole && u_pole && m0_occ && m1_occ && m0_vir && m1_vir,
                  "NULL array argument");
-    if (prec == AGF2_FP64)
-      build_moments_f64(h, nphys, naux, Lpq, npole, nocc_pole, e_pole, u_pole, m0_occ,
-                        m1_occ, m0_vir, m1_vir);
-    else if (prec == AGF2_SPLIT_BF16 || prec == AGF2_SPLIT_FP16)
-      build_moments_split(h, nphys, naux, Lpq, npole, nocc_pole, e_pole, u_pole, m0_occ,
-                          m1_occ, m0_vir, m1_vir, prec == AGF2_SPLIT_FP16);
-    else
-      throw Error{AGF2_ERR_ARG, "unknown precision mode"};
+    build_moments(h, prec, nphys, naux, Lpq, npole, nocc_pole, e_pole, u_pole, m0_occ, m1_occ,
+                  m0_vir, m1_vir);
   });
 }
 
@@ -682,67 +809,16 @@ agf2_status agf2_fock_loop(agf2_handle_t hh, int nphys, int naux, const double* 
     AGF2_REQUIRE(Lpq && hcore && rdm1 && fock && e_pole && u_pole && nocc_pole && mu &&
                      shift && n_cycle && (naux_se == 0 || (e_se && v_se)),
                  "NULL argument");
-    if (nelec <= 0 || nelec % 2 != 0 || nelec >= 2 * (nphys + naux_se))
-      throw Error{AGF2_ERR_NELEC, "nelec must be even and in (0, 2 * npole)"};
     agf2_fock_opts o;
     agf2_fock_opts_default(&o);
     if (opts) o = *opts;
-    AGF2_REQUIRE(o.max_cycle >= 1 && o.tol_rdm1 > 0 && o.tol_nelec > 0 && o.bracket > 0 &&
-                     o.step0 > 0 && o.diis_space >= 0,
-                 "bad Fock-loop options");
-    hipStream_t s = h.stream;
-    const int N = nphys;
-    const long nn = (long)N * N;
-    FockLoop fl(h, N, naux, naux_se, Lpq, e_se, v_se, (double)nelec);
-    double* F = h.ws_fock[6].as<double>(3 * nn);
-    double* Fn = F + nn;
-    double* Dn = Fn + nn;
-    Diis diis(h, nn, o.diis_space, h.ws_fock[7]);
-    fock_build(h, N, naux, Lpq, hcore, rdm1, 1.0, F);
-    double d = 0.0;
-    bool converged = false;
-    int cycle = 0;
-    Aufbau a;
-    for (cycle = 1; cycle <= o.max_cycle; ++cycle) {
-      d = fl.fit_shift(F, d, o);
-      if (!(fl.solved_shift == d && fl.solved_F == F)) fl.solve(F, d);
-      a = aufbau(fl.n, fl.hlam, fl.hw, (double)nelec);
-      // D = 2 sum_{l < n*} phi_l phi_l^T (physical block)
-      Gemm g;
-      g.M = N; g.N = N; g.K = a.n;
-      g.A = fl.H; g.sAm = 1; g.sAk = fl.n;
-      g.B = fl.H; g.sBn = 1; g.sBk = fl.n;
-      g.C = Dn; g.sCm = N; g.sCn = 1; g.alpha = 2.0;
-      if (a.n > 0) gemm_f64(g, s);
-      else AGF2_HIP(hipMemsetAsync(Dn, 0, nn * sizeof(double), s));
-      // RMS change of D
-      hipLaunchKernelGGL(sqdiff_kernel, dim3(nblk(nn)), dim3(256), 0, s, nn, Dn, rdm1, Fn);
-      AGF2_CHECK_LAUNCH();
-      const double err = std::sqrt(dot_f64(h, nn, Fn, Fn) / (double)nn);
-      AGF2_HIP(hipMemcpyAsync(rdm1, Dn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
-      if (err < o.tol_rdm1) { converged = true; break; }
-      fock_build(h, N, naux, Lpq, hcore, rdm1, 1.0, Fn);
-      // error vector F[D] - F, stored in Dn (free now)
-      hipLaunchKernelGGL(sqdiff_kernel, dim3(nblk(nn)), dim3(256), 0, s, nn, Fn, F, Dn);
-      AGF2_CHECK_LAUNCH();
-      diis.update(Fn, Dn);
-      AGF2_HIP(hipMemcpyAsync(F, Fn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
-    if (cycle > o.max_cycle) cycle = o.max_cycle;
-    AGF2_HIP(hipMemcpyAsync(fock, F, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
-    AGF2_HIP(hipMemcpyAsync(e_pole, fl.lam, fl.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    extract_poles(N, fl.n, fl.H, u_pole, s);
-    if (naux_se > 0) {
-      hipLaunchKernelGGL(add_scalar_kernel, dim3(nblk(naux_se)), dim3(256), 0, s,
-                         (long)naux_se, d, e_se);
-      AGF2_CHECK_LAUNCH();
-    }
-    AGF2_HIP(hipStreamSynchronize(s));
-    *nocc_pole = a.n;
-    *mu = a.mu;
-    *shift = d;
-    *n_cycle = cycle;
-    if (!converged) conv = AGF2_ERR_NO_CONVERGE;
+    FockLoopResult r = fock_loop_impl(h, nphys, naux, Lpq, hcore, nelec, naux_se, e_se, v_se,
+                                      rdm1, fock, e_pole, u_pole, o);
+    *nocc_pole = r.nocc_pole;
+    *mu = r.mu;
+    *shift = r.shift;
+    *n_cycle = r.n_cycle;
+    if (!r.converged) conv = AGF2_ERR_NO_CONVERGE;
   });
   if (st == AGF2_OK && conv != AGF2_OK) {
     reinterpret_cast<Handle*>(hh)->last_error = "Fock loop reached max_cycle";
@@ -764,47 +840,8 @@ agf2_status agf2_energy_gf(agf2_handle_t hh, int nphys, const double* hcore, con
     AGF2_REQUIRE((naux_occ == 0 || (e_se_occ && v_se_occ)) &&
                      (naux_vir == 0 || (e_se_vir && v_se_vir)),
                  "NULL auxiliary argument");
-    hipStream_t s = h.stream;
-    const long nn = (long)nphys * nphys;
-    double* part = h.ws_red.as<double>(4096);
-    const int nb1 = nblk(nn);
-    hipLaunchKernelGGL(e1b_kernel, dim3(nb1), dim3(256), 0, s, nn, hcore, fock, rdm1, part);
-    AGF2_CHECK_LAUNCH();
-    const double e1 = reduce_partials(h, part, nb1);
-    double e2 = 0.0;
-    const int nv = npole - nocc_pole;
-    // occupied poles x greater auxiliaries
-    if (nocc_pole > 0 && naux_vir > 0) {
-      double* c = h.ws_misc[6].as<double>((long)nocc_pole * naux_vir);
-      Gemm g;
-      g.M = nocc_pole; g.N = naux_vir; g.K = nphys;
-      g.A = u_pole; g.sAm = 1; g.sAk = npole;
-      g.B = v_se_vir; g.sBn = 1; g.sBk = naux_vir;
-      g.C = c; g.sCm = naux_vir; g.sCn = 1;
-      gemm_f64(g, s);
-      const int nb = nblk((long)nocc_pole * naux_vir);
-      hipLaunchKernelGGL(gm_sum_kernel, dim3(nb), dim3(256), 0, s, nocc_pole, naux_vir, c,
-                         e_pole, e_se_vir, 1.0, part);
-      AGF2_CHECK_LAUNCH();
-      e2 += reduce_partials(h, part, nb);
-    }
-    // virtual poles x lesser auxiliaries: (u_l.v_k)^2 / (e_k - lam_l)
-    if (nv > 0 && naux_occ > 0) {
-      double* c = h.ws_misc[6].as<double>((long)nv * naux_occ);
-      Gemm g;
-      g.M = nv; g.N = naux_occ; g.K = nphys;
-      g.A = u_pole + nocc_pole; g.sAm = 1; g.sAk = npole;
-      g.B = v_se_occ; g.sBn = 1; g.sBk = naux_occ;
-      g.C = c; g.sCm = naux_occ; g.sCn = 1;
-      gemm_f64(g, s);
-      const int nb = nblk((long)nv * naux_occ);
-      hipLaunchKernelGGL(gm_sum_kernel, dim3(nb), dim3(256), 0, s, nv, naux_occ, c,
-                         e_pole + nocc_pole, e_se_occ, -1.0, part);
-      AGF2_CHECK_LAUNCH();
-      e2 += reduce_partials(h, part, nb);
-    }
-    *e_1b = e1;
-    *e_2b = e2;
+    energy_impl(h, nphys, hcore, fock, rdm1, npole, nocc_pole, e_pole, u_pole, naux_occ,
+                e_se_occ, v_se_occ, naux_vir, e_se_vir, v_se_vir, e_1b, e_2b);
   });
 }
 

@@ -111,6 +111,27 @@ struct ProfTotal {
   double ms = 0.0, flops = 0.0, bytes = 0.0;
 };
 
+struct FockLoopResult {
+  int nocc_pole = 0;
+  double mu = 0.0, shift = 0.0;
+  int n_cycle = 0;
+  bool converged = false;
+};
+FockLoopResult fock_loop_impl(Handle& h, int nphys, int naux, const double* Lpq,
+                              const double* hcore, int nelec, int naux_se, double* e_se,
+                              const double* v_se, double* rdm1, double* fock,
+                              double* e_pole, double* u_pole, const agf2_fock_opts& o);
+void energy_impl(Handle& h, int nphys, const double* hcore, const double* fock,
+                 const double* rdm1, int npole, int nocc_pole, const double* e_pole,
+                 const double* u_pole, int naux_occ, const double* e_se_occ,
+                 const double* v_se_occ, int naux_vir, const double* e_se_vir,
+                 const double* v_se_vir, double* e_1b, double* e_2b);
+int compress_part(Handle& h, int N, const double* m0, const double* m1, double tol,
+                  double* e_aux, double* v_aux);
+void build_moments(Handle& h, agf2_precision prec, int N, int Q, const double* L, int npole,
+                   int nocc, const double* e, const double* u, double* m0o, double* m1o,
+                   double* m0v, double* m1v);
+
 struct Handle {
   int device = 0;
   bool profiling = false;
@@ -125,6 +146,7 @@ struct Handle {
   DevBuf ws_moments[8];
   DevBuf ws_fock[8];
   DevBuf ws_misc[8];
+  DevBuf ws_run[8];
   DevBuf ws_red;
   double* host_red = nullptr;   // pinned scratch for small reductions
   size_t host_red_n = 0;
