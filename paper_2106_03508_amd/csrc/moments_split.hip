@@ -148,90 +148,68 @@ __global__ void split_rows_kernel(const double* in, long s_in_a, long s_in_b, in
   }
 }
 
-struct SlabArgs {
-  const u16* Rh; const u16* Rl; long sRp, sRx;   // R[p][x][Qs]
-  const u16* Sh; const u16* Sl; long sSp, sSc;   // S[q][c][Qs]
-  const int* eR;                                 // fp16: exponent of R row group p
-  const int* eS; long sEp, sEc;                  // fp16: exponent of S row (q, c)
-  float zscale, wscale;                          // 2^fZ, 2^fW (1 for bf16)
-  const double* ep; const double* ec;
-  int N, nc, Qs;
-  const int* pi; const int* pj; const long* pcol;
-  int pair0, npairs; long col_base;
-  u16* Zh; u16* Zl; u16* Wh; u16* Wl; long ldz;
-  int tiles_x, tiles_c;
+// Slab as a plain tiled GEMM over blocks of poles:
+//   X[(p, x)][(q, c)] = sum_Q R[p][x][Q] S[q][c][Q]
+// for p in a row block and q in a column block, with rows and columns
+// addressed through (pole, index) pairs. 256x256 output tiles, four waves of
+// 128x128 (8x8 MFMA blocks each), float32 accumulators.
+struct XgemmArgs {
+  const u16* Ah; const u16* Al; long sAp, sAx; int mA;   // row m: (m / mA) sAp + (m % mA) sAx
+  const u16* Bh; const u16* Bl; long sBq, sBc; int nB;   // row n: (n / nB) sBq + (n % nB) sBc
+  int M, Nn, Qs;
+  float* C; long ldc;
+  int tiles_m, tiles_n;
 };
 
-constexpr int TX = 128;   // x rows per slab workgroup (32 per wave)
+constexpr int GT = 256;
 
-template <int CB, bool F16>
-__global__ __launch_bounds__(NT) void slab_split_kernel(SlabArgs a) {
-  constexpr int TC = 16 * CB;
-  __shared__ u16x8 sA[4][TX][KVP];   // R[p] hi, R[p] lo, R[q] hi, R[q] lo
-  __shared__ u16x8 sB[4][TC][KVP];   // S[q] hi, S[q] lo, S[p] hi, S[p] lo
+template <bool F16>
+__global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmArgs a) {
+  __shared__ u16x8 sA[2][GT][KVP];   // hi, lo
+  __shared__ u16x8 sB[2][GT][KVP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long G = (long)a.npairs * a.tiles_x * a.tiles_c;
+  const long G = (long)a.tiles_m * a.tiles_n;
   const long logical = xcd_remap(blockIdx.x, G);
-  const int per_pair = a.tiles_x * a.tiles_c;
-  const int P = a.pair0 + (int)(logical / per_pair);
-  const int rem = (int)(logical % per_pair);
-  const int xt = rem % a.tiles_x, ct = rem / a.tiles_x;
-  const int p = a.pi[P], q = a.pj[P];
-  const bool diag = (p == q);
-  const int x0 = xt * TX, c0 = ct * TC;
+  const int tm = (int)(logical / a.tiles_n), tn = (int)(logical % a.tiles_n);
+  const int m0 = tm * GT, n0 = tn * GT;
   const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-
-  u16x8 ra[8], rb[CB];
+  // loader: per operand 256 rows x 4 vectors; thread -> rows tid/4 + 64 i, vector tid % 4
+  const int kv = tid & 3;
+  long oa[4], ob[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = (tid >> 2) + 64 * i;
+    const int m = m0 + r, n = n0 + r;
+    oa[i] = m < a.M ? (long)(m / a.mA) * a.sAp + (long)(m % a.mA) * a.sAx + 8 * kv : -1;
+    ob[i] = n < a.Nn ? (long)(n / a.nB) * a.sBq + (long)(n % a.nB) * a.sBc + 8 * kv : -1;
+  }
+  u16x8 pa[8], pb[8];
   auto load = [&](int kb) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int idx = tid + NT * i;
-      const int arr = idx / (TX * KV), rr = (idx / KV) % TX, kv = idx % KV;
-      const int x = x0 + rr;
-      const bool use = x < a.N && (arr < 2 || !diag);
-      const u16* base = (arr & 1) ? a.Rl : a.Rh;
-      const int pole = arr < 2 ? p : q;
-      ra[i] = use ? *reinterpret_cast<const u16x8*>(base + (long)pole * a.sRp + (long)x * a.sRx +
-                                                    kb + 8 * kv)
-                  : zero8;
-    }
-#pragma unroll
-    for (int i = 0; i < CB; ++i) {
-      const int idx = tid + NT * i;
-      const int arr = idx / (TC * KV), rr = (idx / KV) % TC, kv = idx % KV;
-      const int c = c0 + rr;
-      const bool use = c < a.nc && (arr < 2 || !diag);
-      const u16* base = (arr & 1) ? a.Sl : a.Sh;
-      const int pole = arr < 2 ? q : p;
-      rb[i] = use ? *reinterpret_cast<const u16x8*>(base + (long)pole * a.sSp + (long)c * a.sSc +
-                                                    kb + 8 * kv)
-                  : zero8;
+    for (int i = 0; i < 4; ++i) {
+      pa[i] = oa[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Ah + oa[i] + kb) : zero8;
+      pa[4 + i] = oa[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Al + oa[i] + kb) : zero8;
+      pb[i] = ob[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Bh + ob[i] + kb) : zero8;
+      pb[4 + i] = ob[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Bl + ob[i] + kb) : zero8;
     }
   };
   auto store = [&]() {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int idx = tid + NT * i;
-      sA[idx / (TX * KV)][(idx / KV) % TX][idx % KV] = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < CB; ++i) {
-      const int idx = tid + NT * i;
-      sB[idx / (TC * KV)][(idx / KV) % TC][idx % KV] = rb[i];
+    for (int i = 0; i < 4; ++i) {
+      const int r = (tid >> 2) + 64 * i;
+      sA[0][r][kv] = pa[i];
+      sA[1][r][kv] = pa[4 + i];
+      sB[0][r][kv] = pb[i];
+      sB[1][r][kv] = pb[4 + i];
     }
   };
-
   const int fr = lane & 15, fk = lane >> 4;
-  const int wr = 32 * wave;
-  f4 c1[2][CB], c2[2][CB];
+  const int wm = (wave & 1) * 128, wn = (wave >> 1) * 128;
+  f4 acc[8][8];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < CB; ++j) {
-      c1[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-      c2[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-
+    for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int nsteps = a.Qs / KS;
   load(0);
   for (int step = 0; step < nsteps; ++step) {
@@ -239,84 +217,91 @@ __global__ __launch_bounds__(NT) void slab_split_kernel(SlabArgs a) {
     store();
     __syncthreads();
     if (step + 1 < nsteps) load((step + 1) * KS);
-    u16x8 ah1[2], al1[2];
+    u16x8 ah[8], al[8];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      ah1[i] = sA[0][wr + 16 * i + fr][fk];
-      al1[i] = sA[1][wr + 16 * i + fr][fk];
+    for (int i = 0; i < 8; ++i) {
+      ah[i] = sA[0][wm + 16 * i + fr][fk];
+      al[i] = sA[1][wm + 16 * i + fr][fk];
     }
 #pragma unroll
-    for (int j = 0; j < CB; ++j) {
-      const u16x8 bh = sB[0][16 * j + fr][fk], bl = sB[1][16 * j + fr][fk];
+    for (int j = 0; j < 8; ++j) {
+      const u16x8 bh = sB[0][wn + 16 * j + fr][fk], bl = sB[1][wn + 16 * j + fr][fk];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        c1[i][j] = mfma<F16>(ah1[i], bh, c1[i][j]);
-        c1[i][j] = mfma<F16>(ah1[i], bl, c1[i][j]);
-        c1[i][j] = mfma<F16>(al1[i], bh, c1[i][j]);
-      }
-    }
-    if (!diag) {
-      u16x8 ah2[2], al2[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ah2[i] = sA[2][wr + 16 * i + fr][fk];
-        al2[i] = sA[3][wr + 16 * i + fr][fk];
-      }
-#pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        const u16x8 bh = sB[2][16 * j + fr][fk], bl = sB[3][16 * j + fr][fk];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          c2[i][j] = mfma<F16>(ah2[i], bh, c2[i][j]);
-          c2[i][j] = mfma<F16>(ah2[i], bl, c2[i][j]);
-          c2[i][j] = mfma<F16>(al2[i], bh, c2[i][j]);
-        }
+      for (int i = 0; i < 8; ++i) {
+        acc[i][j] = mfma<F16>(ah[i], bh, acc[i][j]);
+        acc[i][j] = mfma<F16>(ah[i], bl, acc[i][j]);
+        acc[i][j] = mfma<F16>(al[i], bh, acc[i][j]);
       }
     }
   }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + crow(lane, r);
+        const int n = n0 + wn + 16 * j + fr;
+        if (m < a.M && n < a.Nn) a.C[(long)m * a.ldc + n] = acc[i][j][r];
+      }
+}
 
-  const long col0 = a.pcol[P] - a.col_base;
+// Pairs the slabs of a block pair into Z columns. For pole pair (p, q) of the
+// chunk, X^{pq}[x][c] = (xp|qc) and X^{qp}[x][c] = (xq|pc) are read from the
+// GEMM outputs (X1: rows of block P0, columns of block P1; X2: the mirrored
+// block, or X1 itself when P0 == P1); the Z columns are
+// sqrt(1/2)(X^{pq}+X^{qp}) and sqrt(3/2)(X^{pq}-X^{qp}) (X^{pp} for p = q),
+// each with its weighted copy, stored as 16-bit pairs.
+struct PairArgs {
+  const float* X1; const float* X2; long ld1, ld2;
+  int N, nc, P0, P1;
+  const int* pa; const int* pb; const long* pcol; long col_base; int npairs;
+  const int* eR; const int* eS; long sEp, sEc;
+  float zscale, wscale;
+  const double* ep; const double* ec;
+  u16* Zh; u16* Zl; u16* Wh; u16* Wl; long ldz;
+};
+
+template <bool F16>
+__global__ void pair_split_kernel(PairArgs a) {
+  const long tot = (long)a.npairs * a.N * a.nc;
   // sqrt(1/2) and sqrt(3/2) as float pairs: every column is multiplied with
   // one rounding (fma), so the constants' own float rounding does not bias
   // all P or all M columns alike
   const float cp_hi = 0.707106769084930419921875f, cp_lo = 1.2101617485882343e-08f;
   const float cm_hi = 1.22474491596221923828125f, cm_lo = -4.4570629853524224e-08f;
-  const double epq = a.ep[p] + a.ep[q];
-#pragma unroll
-  for (int j = 0; j < CB; ++j) {
-    const int c = c0 + 16 * j + fr;
-    if (c >= a.nc) continue;
-    const float wgt = (float)(epq - a.ec[c]);
-    // undo the operand scales of the two products (exact powers of two)
-    int e1 = 0, e2 = 0;
-    if constexpr (F16) {
-      e1 = a.eR[p] + a.eS[(long)q * a.sEp + (long)c * a.sEc] - 2 * EMAX;
-      e2 = a.eR[q] + a.eS[(long)p * a.sEp + (long)c * a.sEc] - 2 * EMAX;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(idx % a.nc);
+    const long t = idx / a.nc;
+    const int x = (int)(t % a.N);
+    const int pr = (int)(t / a.N);
+    const int p = a.pa[pr], q = a.pb[pr];
+    const long col = a.pcol[pr] - a.col_base + c;
+    const long o = (long)x * a.ldz + col;
+    float x1 = a.X1[((long)(p - a.P0) * a.N + x) * a.ld1 + (long)(q - a.P1) * a.nc + c];
+    if constexpr (F16)
+      x1 = ldexpf(x1, a.eR[p] + a.eS[(long)q * a.sEp + (long)c * a.sEc] - 2 * EMAX);
+    const float wgt = (float)(a.ep[p] + a.ep[q] - a.ec[c]);
+    u16 h, l;
+    if (p == q) {
+      split<F16>(a.zscale * x1, h, l); a.Zh[o] = h; a.Zl[o] = l;
+      split<F16>(a.wscale * (wgt * x1), h, l); a.Wh[o] = h; a.Wl[o] = l;
+      continue;
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int x = x0 + wr + 16 * i + crow(lane, r);
-        if (x >= a.N) continue;
-        const long o = (long)x * a.ldz + col0 + c;
-        const float x1 = F16 ? ldexpf(c1[i][j][r], e1) : c1[i][j][r];
-        u16 h, l;
-        if (diag) {
-          split<F16>(a.zscale * x1, h, l); a.Zh[o] = h; a.Zl[o] = l;
-          split<F16>(a.wscale * (wgt * x1), h, l); a.Wh[o] = h; a.Wl[o] = l;
-        } else {
-          const float x2 = F16 ? ldexpf(c2[i][j][r], e2) : c2[i][j][r];
-          const float sp = x1 + x2, sm = x1 - x2;
-          const float zp = fmaf(sp, cp_hi, sp * cp_lo);
-          const float zm = fmaf(sm, cm_hi, sm * cm_lo);
-          split<F16>(a.zscale * zp, h, l); a.Zh[o] = h; a.Zl[o] = l;
-          split<F16>(a.wscale * (wgt * zp), h, l); a.Wh[o] = h; a.Wl[o] = l;
-          const long om = o + a.nc;
-          split<F16>(a.zscale * zm, h, l); a.Zh[om] = h; a.Zl[om] = l;
-          split<F16>(a.wscale * (wgt * zm), h, l); a.Wh[om] = h; a.Wl[om] = l;
-        }
-      }
+    float x2 = (a.P0 == a.P1)
+                   ? a.X1[((long)(q - a.P0) * a.N + x) * a.ld1 + (long)(p - a.P1) * a.nc + c]
+                   : a.X2[((long)(q - a.P1) * a.N + x) * a.ld2 + (long)(p - a.P0) * a.nc + c];
+    if constexpr (F16)
+      x2 = ldexpf(x2, a.eR[q] + a.eS[(long)p * a.sEp + (long)c * a.sEc] - 2 * EMAX);
+    const float sp = x1 + x2, sm = x1 - x2;
+    const float zp = fmaf(sp, cp_hi, sp * cp_lo);
+    const float zm = fmaf(sm, cm_hi, sm * cm_lo);
+    split<F16>(a.zscale * zp, h, l); a.Zh[o] = h; a.Zl[o] = l;
+    split<F16>(a.wscale * (wgt * zp), h, l); a.Wh[o] = h; a.Wl[o] = l;
+    const long om = o + a.nc;
+    split<F16>(a.zscale * zm, h, l); a.Zh[om] = h; a.Zl[om] = l;
+    split<F16>(a.wscale * (wgt * zm), h, l); a.Wh[om] = h; a.Wl[om] = l;
   }
 }
 
@@ -476,46 +461,6 @@ __global__ __launch_bounds__(NT) void syrk_split_kernel(SyrkArgs a) {
       }
 }
 
-struct PairTable {
-  std::vector<int> pi, pj;
-  std::vector<long> col;
-};
-
-PairTable make_pairs(int np, int nc) {
-  PairTable t;
-  long c = 0;
-  for (int p = 0; p < np; ++p)
-    for (int q = p; q < np; ++q) {
-      t.pi.push_back(p); t.pj.push_back(q); t.col.push_back(c);
-      c += (p == q) ? nc : 2L * nc;
-    }
-  t.col.push_back(c);
-  return t;
-}
-
-int pick_cb(int nc) {
-  const int cands[4] = {8, 6, 5, 4};
-  int best = 4;
-  long best_cols = -1;
-  for (int cb : cands) {
-    const long w = 16L * cb;
-    const long cols = (nc + w - 1) / w * w;
-    if (best_cols < 0 || cols < best_cols) { best_cols = cols; best = cb; }
-  }
-  return best;
-}
-
-template <bool F16>
-void launch_slab(int cb, long G, hipStream_t st, const SlabArgs& sa) {
-  switch (cb) {
-    case 4: hipLaunchKernelGGL((slab_split_kernel<4, F16>), dim3((unsigned)G), dim3(NT), 0, st, sa); break;
-    case 5: hipLaunchKernelGGL((slab_split_kernel<5, F16>), dim3((unsigned)G), dim3(NT), 0, st, sa); break;
-    case 6: hipLaunchKernelGGL((slab_split_kernel<6, F16>), dim3((unsigned)G), dim3(NT), 0, st, sa); break;
-    default: hipLaunchKernelGGL((slab_split_kernel<8, F16>), dim3((unsigned)G), dim3(NT), 0, st, sa); break;
-  }
-  AGF2_CHECK_LAUNCH();
-}
-
 template <bool F16>
 void split_rows(const double* in, long s_in_a, long s_in_b, int na, int nb, const int* perm,
                 u16* hi, u16* lo, long s_out_a, long s_out_b, int Qs, const int* gexp, long gsa,
@@ -583,23 +528,46 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
     AGF2_HIP(hipMemsetAsync(U1, 0, nn * sizeof(double), st));
     return;
   }
-  PairTable t = make_pairs(np, nc);
-  const int npairs = (int)t.pi.size();
-  int* d_pi = h.ws_moments[6].as<int>(2L * npairs);
-  int* d_pj = d_pi + npairs;
-  long* d_col = h.ws_moments[7].as<long>(npairs + 1);
-  AGF2_HIP(hipMemcpyAsync(d_pi, t.pi.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
-  AGF2_HIP(hipMemcpyAsync(d_pj, t.pj.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
-  AGF2_HIP(hipMemcpyAsync(d_col, t.col.data(), (npairs + 1) * sizeof(long),
-                          hipMemcpyHostToDevice, st));
+  // blocks of kb poles; a chunk is one block pair (ib <= jb), whose slabs
+  // X1 = R[block ib] S[block jb]^T and X2 = R[block jb] S[block ib]^T are
+  // float32 buffers of kb N x kb nc each (<= ~256 MiB)
+  int kb = (int)std::floor(std::sqrt((double)(1L << 26) / ((double)N * nc)));
+  kb = std::max(1, std::min(kb, np));
+  const int nblk = (np + kb - 1) / kb;
+  // pair list ordered by block pair, with chunk-local column offsets
+  std::vector<int> hpa, hpb;
+  std::vector<long> hcol;
+  std::vector<long> chunk_first, chunk_cols;
+  for (int ib = 0; ib < nblk; ++ib)
+    for (int jb = ib; jb < nblk; ++jb) {
+      chunk_first.push_back((long)hpa.size());
+      long c0 = 0;
+      for (int p = ib * kb; p < std::min(np, (ib + 1) * kb); ++p)
+        for (int q = jb * kb; q < std::min(np, (jb + 1) * kb); ++q) {
+          if (ib == jb && q < p) continue;
+          hpa.push_back(p); hpb.push_back(q); hcol.push_back(c0);
+          c0 += (p == q) ? nc : 2L * nc;
+        }
+      chunk_cols.push_back(c0);
+    }
+  const long npairs = (long)hpa.size();
+  int* d_pa = h.ws_moments[6].as<int>(2 * npairs);
+  int* d_pb = d_pa + npairs;
+  long* d_col = h.ws_moments[7].as<long>(npairs);
+  AGF2_HIP(hipMemcpyAsync(d_pa, hpa.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
+  AGF2_HIP(hipMemcpyAsync(d_pb, hpb.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
+  AGF2_HIP(hipMemcpyAsync(d_col, hcol.data(), npairs * sizeof(long), hipMemcpyHostToDevice, st));
   AGF2_HIP(hipStreamSynchronize(st));   // host tables go out of scope below
 
-  const long cap_bytes = 512L << 20;   // Z chunk: 4 arrays of 16-bit values
-  long kcap = std::max<long>(2L * nc, cap_bytes / (8L * N));
-  kcap = std::min<long>(kcap, t.col.back());
+  long kcap = 0;
+  for (long c : chunk_cols) kcap = std::max(kcap, c);
   kcap = (kcap + KS - 1) / KS * KS;
   u16* Z = h.ws_moments[4].as<u16>(4L * N * kcap);
   u16 *Zh = Z, *Zl = Z + (long)N * kcap, *Wh = Z + 2L * N * kcap, *Wl = Z + 3L * N * kcap;
+  const long xel = (long)kb * N * (long)kb * nc;
+  float* X = reinterpret_cast<float*>(h.ws_moments[3].as<double>(xel + 8));   // X1, X2
+  float* X1 = X;
+  float* X2 = X + xel;
 
   const int tiles_n = (N + TS - 1) / TS;
   const int nlower = tiles_n * (tiles_n + 1) / 2;
@@ -608,47 +576,63 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
   double* part = h.ws_moments[5].as<double>(part_stride * nsplit_max);
   AGF2_HIP(hipMemsetAsync(part, 0, part_stride * nsplit_max * sizeof(double), st));
 
-  const int cb = pick_cb(nc);
-  const int tiles_x = (N + TX - 1) / TX, tiles_c = (nc + 16 * cb - 1) / (16 * cb);
-  int P0 = 0;
-  while (P0 < npairs) {
-    int P1 = P0;
-    while (P1 < npairs && t.col[P1 + 1] - t.col[P0] <= kcap) ++P1;
-    if (P1 == P0) P1 = P0 + 1;
-    const long Kc = t.col[P1] - t.col[P0];
-    SlabArgs sa;
-    sa.Rh = Rh; sa.Rl = Rl; sa.sRp = sRp; sa.sRx = sRx;
-    sa.Sh = Sh; sa.Sl = Sl; sa.sSp = sSp; sa.sSc = sSc;
-    sa.eR = sc.eR; sa.eS = sc.eS; sa.sEp = sc.sEp; sa.sEc = sc.sEc;
-    sa.zscale = sc.zscale; sa.wscale = sc.wscale;
-    sa.ep = ep; sa.ec = ec; sa.N = N; sa.nc = nc; sa.Qs = Qs;
-    sa.pi = d_pi; sa.pj = d_pj; sa.pcol = d_col;
-    sa.pair0 = P0; sa.npairs = P1 - P0; sa.col_base = t.col[P0];
-    sa.Zh = Zh; sa.Zl = Zl; sa.Wh = Wh; sa.Wl = Wl; sa.ldz = kcap;
-    sa.tiles_x = tiles_x; sa.tiles_c = tiles_c;
-    long nd = 0;
-    for (int P = P0; P < P1; ++P) nd += (t.pi[P] == t.pj[P]);
-    const double slabs = 2.0 * (P1 - P0) - (double)nd;
-    {
-      ProfScope ps(h, "moments.slab", slabs * 2.0 * N * nc * Q, 8.0 * (N + 0.0) * Kc);
-      launch_slab<F16>(cb, (long)sa.npairs * tiles_x * tiles_c, st, sa);
+  auto gemm = [&](int prow, int nrow, int pcol, int ncol, float* C) {
+    XgemmArgs g;
+    g.Ah = Rh + (long)prow * sRp; g.Al = Rl + (long)prow * sRp; g.sAp = sRp; g.sAx = sRx; g.mA = N;
+    g.Bh = Sh + (long)pcol * sSp; g.Bl = Sl + (long)pcol * sSp; g.sBq = sSp; g.sBc = sSc;
+    g.nB = nc;
+    g.M = nrow * N; g.Nn = ncol * nc; g.Qs = Qs;
+    g.C = C; g.ldc = (long)ncol * nc;
+    g.tiles_m = (g.M + GT - 1) / GT; g.tiles_n = (g.Nn + GT - 1) / GT;
+    ProfScope ps(h, "moments.slab", 2.0 * g.M * (double)g.Nn * Q,
+                 4.0 * ((double)g.M + g.Nn) * Qs + 4.0 * (double)g.M * g.Nn);
+    hipLaunchKernelGGL((xgemm_split_kernel<F16>), dim3((unsigned)((long)g.tiles_m * g.tiles_n)),
+                       dim3(NT), 0, st, g);
+    AGF2_CHECK_LAUNCH();
+  };
+
+  int chunk = 0;
+  for (int ib = 0; ib < nblk; ++ib)
+    for (int jb = ib; jb < nblk; ++jb, ++chunk) {
+      const int P0 = ib * kb, na = std::min(kb, np - P0);
+      const int P1 = jb * kb, nb = std::min(kb, np - P1);
+      gemm(P0, na, P1, nb, X1);
+      if (ib != jb) gemm(P1, nb, P0, na, X2);
+      const long first = chunk_first[chunk];
+      const long last = (chunk + 1 < (int)chunk_first.size()) ? chunk_first[chunk + 1] : npairs;
+      const long Kc = chunk_cols[chunk];
+      PairArgs pa;
+      pa.X1 = X1; pa.X2 = X2; pa.ld1 = (long)nb * nc; pa.ld2 = (long)na * nc;
+      pa.N = N; pa.nc = nc; pa.P0 = P0; pa.P1 = P1;
+      pa.pa = d_pa + first; pa.pb = d_pb + first; pa.pcol = d_col + first; pa.col_base = 0;
+      pa.npairs = (int)(last - first);
+      pa.eR = sc.eR; pa.eS = sc.eS; pa.sEp = sc.sEp; pa.sEc = sc.sEc;
+      pa.zscale = sc.zscale; pa.wscale = sc.wscale;
+      pa.ep = ep; pa.ec = ec;
+      pa.Zh = Zh; pa.Zl = Zl; pa.Wh = Wh; pa.Wl = Wl; pa.ldz = kcap;
+      {
+        const long tot = (long)pa.npairs * N * nc;
+        ProfScope ps(h, "moments.pair", 0.0, 4.0 * 2.0 * tot + 8.0 * N * (double)Kc);
+        hipLaunchKernelGGL((pair_split_kernel<F16>),
+                           dim3((unsigned)std::min<long>((tot + 255) / 256, 65536)), dim3(256), 0,
+                           st, pa);
+        AGF2_CHECK_LAUNCH();
+      }
+      int nsplit = (int)std::min<long>(nsplit_max, std::max<long>(1, Kc / 1024));
+      long kper = (Kc + nsplit - 1) / nsplit;
+      kper = (kper + KS - 1) / KS * KS;
+      nsplit = (int)((Kc + kper - 1) / kper);
+      SyrkArgs ya;
+      ya.Zh = Zh; ya.Zl = Zl; ya.Wh = Wh; ya.Wl = Wl; ya.ldz = kcap;
+      ya.N = N; ya.K = Kc; ya.kper = kper;
+      ya.u0scale = sc.u0scale; ya.u1scale = sc.u1scale;
+      ya.part = part; ya.part_stride = part_stride;
+      {
+        ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 0.0) * Kc);
+        hipLaunchKernelGGL((syrk_split_kernel<F16>), dim3(nlower, nsplit), dim3(NT), 0, st, ya);
+        AGF2_CHECK_LAUNCH();
+      }
     }
-    int nsplit = (int)std::min<long>(nsplit_max, std::max<long>(1, Kc / 1024));
-    long kper = (Kc + nsplit - 1) / nsplit;
-    kper = (kper + KS - 1) / KS * KS;
-    nsplit = (int)((Kc + kper - 1) / kper);
-    SyrkArgs ya;
-    ya.Zh = Zh; ya.Zl = Zl; ya.Wh = Wh; ya.Wl = Wl; ya.ldz = kcap;
-    ya.N = N; ya.K = Kc; ya.kper = kper;
-    ya.u0scale = sc.u0scale; ya.u1scale = sc.u1scale;
-    ya.part = part; ya.part_stride = part_stride;
-    {
-      ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 0.0) * Kc);
-      hipLaunchKernelGGL((syrk_split_kernel<F16>), dim3(nlower, nsplit), dim3(NT), 0, st, ya);
-      AGF2_CHECK_LAUNCH();
-    }
-    P0 = P1;
-  }
   ProfScope ps(h, "moments.reduce", 0.0, 8.0 * (2.0 * nsplit_max + 2.0) * nn);
   reduce_moment_partials(part, part_stride, nsplit_max, N, U0, U1, st);
 }
