@@ -9,6 +9,13 @@ energy, all through the C ABI of libagf2.so. Inputs are resident in HBM
 before the timed region. The printed value is the moment build's throughput
 in canonical TFLOP/s, F = 2 N o v (o + v) (Q + 2N) per build; the iteration
 wall time is reported beside it.
+
+With --workload batch64 a step is instead one batched FP64 moment build over
+64 systems of uneven size (nmo uniform in [40, 160], nocc = nmo/5, naux =
+3.5 nmo) in one replay of the library's captured HIP graph, and the value is
+systems per second; --batch-poles picks the pole sets (mean-field poles as at
+the first iteration, or 3N dressed poles with N + nocc occupied, the shape of
+every later iteration).
 """
 from __future__ import annotations
 
@@ -26,7 +33,8 @@ sys.path.insert(0, ROOT)
 
 from paper_2106_03508_amd import synthetic as syn  # noqa: E402
 
-WORKLOADS = {"small": syn.SMALL, "medium": syn.MEDIUM, "large": syn.LARGE, "eval400": syn.EVAL400}
+WORKLOADS = {"batch64": syn.BATCH64, "small": syn.SMALL, "medium": syn.MEDIUM, "large": syn.LARGE,
+             "eval400": syn.EVAL400}
 SEEDS = {"small": 0, "medium": 1, "large": 2, "eval400": 20000}
 PEAK_TFLOPS = {"fp64": 78.6, "split_bf16": 2500.0, "split_fp16": 2500.0}
 
@@ -85,6 +93,110 @@ def cpu_baseline(L, eps, nocc, n_occ_sample, n_vir_sample, log):
                         measured_s=t_tr + t_o + t_v)
 
 
+def batch_systems(poles, threads=16):
+    """The 64-system batch: (L, e_pole, u_pole, nocc_pole) per system."""
+    shapes = syn.batch_shapes(**syn.BATCH64)
+
+    def one(s):
+        N, nocc = s["nmo"], s["nocc"]
+        L = syn.df_tensor(s["seed"], N, s["naux"], nocc)
+        if poles == "hf":
+            return L, syn.orbital_energies(s["seed"], N, nocc), np.eye(N), nocc
+        e, u = syn.random_poles(s["seed"], N, 3 * N, N + nocc)
+        return L, e, u, N + nocc
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, shapes))
+
+
+def batch_flops(systems):
+    return [canonical_flops(L.shape[1], no, e.shape[0] - no, L.shape[0])
+            for L, e, u, no in systems]
+
+
+def main_batch(args):
+    import torch
+    from paper_2106_03508_amd import agf2
+
+    t0 = time.perf_counter()
+    systems = batch_systems(args.batch_poles)
+    flops = batch_flops(systems)
+    F = float(sum(flops))
+    log(f"generated 64 systems ({args.batch_poles} poles) in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda", 0)
+    sd = [(torch.from_numpy(L).to(dev), torch.from_numpy(e).to(dev),
+           torch.from_numpy(np.ascontiguousarray(u)).to(dev), no) for L, e, u, no in systems]
+    h = agf2.Handle(0)
+    outs = None
+    t0 = time.perf_counter()
+    outs, tw = agf2.agf2_build_moments_batched(h, sd, outs)
+    torch.cuda.synchronize()
+    log(f"plan + autotune + capture + first replay {time.perf_counter() - t0:.1f}s; "
+        f"tile widths {sorted(set(tw))}")
+    for _ in range(args.warmup):
+        agf2.agf2_build_moments_batched(h, sd, outs)
+    torch.cuda.synchronize()
+    agf2.agf2_profile_enable(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        agf2.agf2_build_moments_batched(h, sd, outs)
+        torch.cuda.synchronize()
+        log(f"step {k + 1}/{args.steps}")
+    elapsed = time.perf_counter() - t0
+    prof = agf2.agf2_profile_read(h)
+    agf2.agf2_profile_enable(h, False)
+    d = prof["moments.batched"]
+    avg_ms = d["ms"] / d["launches"]
+    achieved = F / (avg_ms * 1e-3) / 1e12
+    ms_step = 1e3 * elapsed / args.steps
+    sizes = [L.shape[1] for L, *_ in systems]
+    out = {
+        "metric": "batched moment build throughput, 64 systems of uneven size",
+        "value": round(64.0 / (ms_step / 1e3), 4),
+        "unit": "systems/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded generator; no molecular integrals)",
+        "config": {"workload": "64 systems, nmo uniform in [40,160] (mean "
+                               f"{np.mean(sizes):.1f}), nocc=nmo/5, naux=3.5 nmo, seeds "
+                               f"1000-1063, {args.batch_poles} poles",
+                   "precision": "fp64", "parallelism": "1 GPU"},
+        "canonical_flops": F,
+        "canonical_tflops": round(F / (ms_step / 1e3) / 1e12, 3),
+        "tile_widths": {str(w): tw.count(w) for w in sorted(set(tw))},
+        "roofline": {"kernel": "moments.batched (one graph replay)", "bound": "mfma",
+                     "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp64"], 4),
+                     "traffic": None, "avg_launch_ms": round(avg_ms, 3),
+                     "flops_per_launch": F},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import agf2_oracle as O
+        log("timing the oracle on a sample of the batch")
+        t_s, f_s, n = 0.0, 0.0, 0
+        for (L, e, u, no), f in zip(systems, flops):
+            t0 = time.perf_counter()
+            O.se_moments(L, e, u, no)
+            t_s += time.perf_counter() - t0
+            f_s += f
+            n += 1
+            log(f"oracle system {n} (nmo={L.shape[1]}) cumulative {t_s:.1f}s")
+            if t_s >= args.cpu_seconds:
+                break
+        rate = f_s / t_s
+        out["cpu_baseline"] = {
+            "value": round(rate / (F / 64.0), 6), "unit": "systems/s", "cores": blas_threads(),
+            "kind": "oracle",
+            "sample": (f"oracle moment build of the first {n} systems of the batch "
+                       f"({t_s:.1f}s, {rate / 1e12:.3f} TFLOP/s canonical), scaled to the "
+                       "batch's mean canonical flops per system"),
+        }
+    print(json.dumps(out), flush=True)
+
+
 def log(msg):
     print(f"# {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
@@ -100,6 +212,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-occ-sample", type=int, default=1)
     ap.add_argument("--cpu-vir-sample", type=int, default=1)
+    ap.add_argument("--batch-poles", default="dressed3n", choices=["hf", "dressed3n"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="batch64: wall time budget of the oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -109,6 +224,8 @@ def main():
     import torch
     from paper_2106_03508_amd import agf2
 
+    if args.workload == "batch64":
+        return main_batch(args)
     wl = WORKLOADS[args.workload]
     N, nocc, Q = wl["nmo"], wl["nocc"], wl["naux"]
     seed = SEEDS[args.workload] if args.seed is None else args.seed

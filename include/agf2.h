@@ -207,6 +207,34 @@ agf2_status agf2_energy_gf(agf2_handle_t handle, int nphys,
                            const double* e_se_vir, const double* v_se_vir,
                            double* e_1b, double* e_2b);
 
+/* One system of a batched moment build (all pointers device, row-major,
+ * float64; meaning as in agf2_build_moments). */
+typedef struct {
+  int nphys, naux;
+  const double* Lpq;                 /* [naux][nphys][nphys] */
+  int npole, nocc_pole;
+  const double* e_pole;              /* [npole] */
+  const double* u_pole;              /* [nphys][npole] */
+  double *m0_occ, *m1_occ, *m0_vir, *m1_vir;   /* [nphys][nphys] outputs */
+} agf2_system;
+
+/*
+ * Moments of many systems of uneven size in one replay of a captured HIP
+ * graph (float64 arithmetic, same definition as agf2_build_moments). All
+ * systems' pole-pair slab tiles go through one persistent grouped launch per
+ * inner-tile width and all contraction tiles through one persistent grouped
+ * launch, work items sorted by cost. The first call with a given batch (sizes
+ * and pointers) plans the workspace, picks the slab inner-tile width (16, 32
+ * or 64 columns) per size bucket by timing each candidate on the batch itself
+ * (project autotuner), captures the graph and replays it; later calls with
+ * the same batch only replay. tile_width (host [nsys], or NULL) receives the
+ * width chosen for each system's greater part.
+ * Errors: AGF2_ERR_ARG (sizes, NULL pointers, nsys < 1), AGF2_ERR_NOMEM.
+ */
+agf2_status agf2_build_moments_batched(agf2_handle_t handle, int nsys,
+                                       const agf2_system* systems,
+                                       int* tile_width);
+
 /* Options of the outer self-consistent loop. */
 typedef struct {
   int max_iter;           /* iterations after iteration 0                    */

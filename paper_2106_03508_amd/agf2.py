@@ -50,12 +50,19 @@ class IterRecord(ctypes.Structure):
                 ("t_moments", _D), ("t_compress", _D), ("t_fock", _D), ("t_energy", _D)]
 
 
+class System(ctypes.Structure):
+    _fields_ = [("nphys", _I), ("naux", _I), ("Lpq", _P), ("npole", _I), ("nocc_pole", _I),
+                ("e_pole", _P), ("u_pole", _P), ("m0_occ", _P), ("m1_occ", _P),
+                ("m0_vir", _P), ("m1_vir", _P)]
+
+
 SIGNATURES = {
     "agf2_create": (_I, [ctypes.POINTER(_P), _I, _P]),
     "agf2_destroy": (_I, [_P]),
     "agf2_last_error": (ctypes.c_char_p, [_P]),
     "agf2_synchronize": (_I, [_P]),
     "agf2_build_moments": (_I, [_P, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P, _P]),
+    "agf2_build_moments_batched": (_I, [_P, _I, ctypes.POINTER(System), _IP]),
     "agf2_fock_build": (_I, [_P, _I, _I, _P, _P, _P, _D, _P]),
     "agf2_compress": (_I, [_P, _I, _P, _P, _D, _IP, _P, _P]),
     "agf2_fock_opts_default": (None, [ctypes.POINTER(FockOpts)]),
@@ -169,6 +176,30 @@ def agf2_build_moments(h: Handle, L, e_pole, u_pole, nocc_pole: int, prec="fp64"
         h.h, p, nphys, naux, _ptr(L, "L", d), npole, nocc_pole, _ptr(e_pole, "e_pole", d),
         _ptr(u_pole, "u_pole", d), *[_ptr(m, "moment", d) for m in out]))
     return out
+
+
+def agf2_build_moments_batched(h: Handle, systems, outs=None):
+    """FP64 moments of a batch of systems in one replayed HIP graph.
+
+    ``systems`` is a sequence of (L, e_pole, u_pole, nocc_pole). Returns
+    (outs, tile_width): outs[s] = (m0_occ, m1_occ, m0_vir, m1_vir) and
+    tile_width[s] the slab inner-tile width the library chose for system s.
+    The library reuses its captured graph while the sizes and the buffers are
+    the same as in the previous call, so pass the same tensors (and ``outs``)
+    again to replay it with new values.
+    """
+    d = h.device
+    n = len(systems)
+    if outs is None:
+        outs = [tuple(h.empty(L.shape[1], L.shape[1]) for _ in range(4)) for L, *_ in systems]
+    arr = (System * n)()
+    for k, ((L, e, u, nocc), out) in enumerate(zip(systems, outs)):
+        naux, nphys, _ = L.shape
+        arr[k] = System(nphys, naux, _ptr(L, "L", d), e.shape[0], int(nocc), _ptr(e, "e_pole", d),
+                        _ptr(u, "u_pole", d), *[_ptr(m, "moment", d) for m in out])
+    tw = (_I * n)()
+    h._check(h.lib.agf2_build_moments_batched(h.h, n, arr, tw))
+    return outs, list(tw)
 
 
 def agf2_fock_build(h: Handle, L, hcore, rdm1, alpha=1.0, out=None):

@@ -79,6 +79,7 @@ static void prof_flush(Handle& h) {
 
 Handle::~Handle() {
   (void)hipDeviceSynchronize();
+  destroy_batch_plan(batch);
   for (auto& r : prof_pending) {
     (void)hipEventDestroy(r.start);
     (void)hipEventDestroy(r.stop);

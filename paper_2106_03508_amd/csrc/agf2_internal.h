@@ -77,6 +77,46 @@ void sum_slices(const double* in, long slice_stride, int nslice, long n,
                 double* out, double scale, bool add, hipStream_t stream);
 
 // ---------------------------------------------------------------- moments
+// FP64 slab tile job: pole pairs pair0.. of one part of one system.
+struct SlabF64 {
+  const double* R; long sRp, sRx;   // R[p][x][Qp]
+  const double* S; long sSp, sSc;   // S[q][c][Qp]
+  const double* ep; const double* ec;
+  int N, nc, Qp;
+  const int* pi; const int* pj; const long* pcol;
+  int pair0, npairs; long col_base;
+  double* Z; long ldz; double* w;
+  int tiles_x, tiles_c;             // tiles_c for the chosen inner tile width
+};
+// FP64 SYRK job: lower-triangle tiles of U0 += Z Z^T, U1 += Z diag(w) Z^T.
+struct SyrkF64 {
+  const double* Z; long ldz; const double* w;
+  int N; long K; long kper; int nsplit;
+  double* part; long part_stride;   // per split: [2][N][N]
+  int tiles;                        // lower-triangle tile count
+};
+int slab_f64_tc(int nc);            // default inner tile width for nc
+long slab_f64_tiles(const SlabF64& a);
+void launch_slab_f64(int tc, const SlabF64& a, hipStream_t st);
+void launch_syrk_f64(const SyrkF64& a, hipStream_t st);
+// Persistent grouped launches over `njobs` jobs: job j owns the global work
+// indices [prefix[j], prefix[j+1]) (its tiles in order; prefix[njobs] =
+// total), and `grid` workgroups stride over [0, total). A SYRK job's local
+// index l is tile l % tiles of K split l / tiles.
+void launch_slab_f64_grouped(int tc, const SlabF64* jobs, const long* prefix, int njobs,
+                             long total, int grid, hipStream_t st);
+void launch_syrk_f64_grouped(const SyrkF64* jobs, const long* prefix, int njobs, long total,
+                             int grid, hipStream_t st);
+// Workgroups that fill the device for a grouped launch (kind 0 slab of width
+// tc, kind 1 SYRK): compute units x resident workgroups per unit.
+int grouped_grid_f64(int kind, int tc);
+void fill_zero(double* p, long n, hipStream_t st);
+void reduce_moment_partials(const double* part, long part_stride, int nsplit, int N,
+                            double* U0, double* U1, hipStream_t st);
+void pole_transform_f64(Handle& h, int N, int Q, int Qp, const double* L, const double* u,
+                        int npole, int p0, int np, double* T);
+void lov_transform_f64(int N, int Q, int Qp, const double* u, int npole, int o, int v,
+                       const double* Lxv, double* Lov, hipStream_t st);
 void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
                        int nocc, const double* e, const double* u, double* m0o,
                        double* m1o, double* m0v, double* m1v);
@@ -132,8 +172,12 @@ void build_moments(Handle& h, agf2_precision prec, int N, int Q, const double* L
                    int nocc, const double* e, const double* u, double* m0o, double* m1o,
                    double* m0v, double* m1v);
 
+struct BatchPlan;   // batched moment build (moments_batched.hip)
+void destroy_batch_plan(BatchPlan* p);
+
 struct Handle {
   int device = 0;
+  BatchPlan* batch = nullptr;
   bool profiling = false;
   std::vector<ProfRecord> prof_pending;
   std::map<std::string, ProfTotal> prof_total;

@@ -10,23 +10,23 @@
 //   X^{pq}(2X^{pq}-X^{qp})^T + X^{qp}(2X^{qp}-X^{pq})^T
 //     = 1/2 (X^{pq}+X^{qp})(...)^T + 3/2 (X^{pq}-X^{qp})(...)^T,
 // and X^{pp} X^{pp T} for p = q. The build therefore runs in two kernels:
-//   slab:  one workgroup owns a pair p<q and an (x, c) tile. It forms
-//          X^{pq} and X^{qp} for that tile in two MFMA accumulators over Q
-//          (LDS-staged operand tiles), so each exchange partner (xq|pc)
-//          sits in the same lane and register as its direct term (xp|qc).
-//          The epilogue writes the columns sqrt(1/2)(X^{pq}+X^{qp}) and
+//   slab:  one workgroup owns a pair p<q and an (x, c) tile (64 x TC). It
+//          forms X^{pq} and X^{qp} for that tile in two MFMA accumulators over
+//          Q (LDS-staged operand tiles), so each exchange partner (xq|pc) sits
+//          in the same lane and register as its direct term (xp|qc). The
+//          epilogue writes the columns sqrt(1/2)(X^{pq}+X^{qp}) and
 //          sqrt(3/2)(X^{pq}-X^{qp}) of Z and their weight.
 //   syrk:  U0 += Z Z^T and U1 += Z diag(w) Z^T on lower-triangle tiles,
 //          split over K into per-split float64 partials (no atomics).
-// Z is produced and consumed in chunks of whole pairs; partials are summed
-// in a fixed order at the end, so results are bitwise reproducible.
+// Tile bodies are device functions shared by one-job launches and by the
+// persistent grouped launches of the batched build. Partials are summed in a
+// fixed order, so results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
 
 #include "agf2_internal.h"
 
 namespace agf2 {
-void gemm_f64_padded(const Gemm& g, int Npad, hipStream_t stream);
 
 namespace {
 
@@ -41,30 +41,20 @@ __device__ __forceinline__ long xcd_remap(long w, long G) {
   return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
-struct SlabArgs {
-  const double* R; long sRp, sRx;   // R[p][x][Q]
-  const double* S; long sSp, sSc;   // S[q][c][Q]
-  const double* ep; const double* ec;
-  int N, nc, Qp;
-  const int* pi; const int* pj; const long* pcol;
-  int pair0, npairs; long col_base;
-  double* Z; long ldz; double* w;
-  int tiles_x, tiles_c;
-};
-
-__global__ __launch_bounds__(NT) void slab_f64_kernel(SlabArgs a) {
-  __shared__ double A1[2][BK][LD], A2[2][BK][LD], B1[2][BK][LD], B2[2][BK][LD];
+// One slab tile: 64 x rows x TC inner columns of pair logical / per_pair.
+// Wave w owns rows 16w..16w+15 and all TC/16 column blocks.
+template <int TC>
+__device__ void slab_tile(const SlabF64& a, long logical, double (*A1)[BK][LD],
+                          double (*A2)[BK][LD], double (*B1)[BK][LD], double (*B2)[BK][LD]) {
+  constexpr int CB = TC / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long G = (long)a.npairs * a.tiles_x * a.tiles_c;
-  const long logical = xcd_remap(blockIdx.x, G);
   const int per_pair = a.tiles_x * a.tiles_c;
   const int P = a.pair0 + (int)(logical / per_pair);
   const int rem = (int)(logical % per_pair);
   const int xt = rem % a.tiles_x, ct = rem / a.tiles_x;
   const int p = a.pi[P], q = a.pj[P];
   const bool diag = (p == q);
-  const int x0 = xt * TB, c0 = ct * TB;
-
+  const int x0 = xt * TB, c0 = ct * TC;
   const double* Rp = a.R + (long)p * a.sRp;
   const double* Rq = a.R + (long)q * a.sRp;
   const double* Sq = a.S + (long)q * a.sSp;
@@ -72,44 +62,47 @@ __global__ __launch_bounds__(NT) void slab_f64_kernel(SlabArgs a) {
 
   // loader: thread -> k = tid % 16, rows tid/16 + 16 i
   const int lk = tid & 15, lr = tid >> 4;
-  double r1[4], r2[4], s1[4], s2[4];
+  double r1[4], r2[4], s1[CB], s2[CB];
   auto load = [&](int kb) {
+    const int k = kb + lk;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int x = x0 + lr + 16 * i, c = c0 + lr + 16 * i, k = kb + lk;
-      const bool xin = x < a.N, cin = c < a.nc;
+      const int x = x0 + lr + 16 * i;
+      const bool xin = x < a.N;
       r1[i] = xin ? Rp[(long)x * a.sRx + k] : 0.0;
+      r2[i] = (xin && !diag) ? Rq[(long)x * a.sRx + k] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int c = c0 + lr + 16 * i;
+      const bool cin = c < a.nc;
       s1[i] = cin ? Sq[(long)c * a.sSc + k] : 0.0;
-      if (!diag) {
-        r2[i] = xin ? Rq[(long)x * a.sRx + k] : 0.0;
-        s2[i] = cin ? Sp[(long)c * a.sSc + k] : 0.0;
-      }
+      s2[i] = (cin && !diag) ? Sp[(long)c * a.sSc + k] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       A1[buf][lk][lr + 16 * i] = r1[i];
+      A2[buf][lk][lr + 16 * i] = r2[i];
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
       B1[buf][lk][lr + 16 * i] = s1[i];
-      if (!diag) {
-        A2[buf][lk][lr + 16 * i] = r2[i];
-        B2[buf][lk][lr + 16 * i] = s2[i];
-      }
+      B2[buf][lk][lr + 16 * i] = s2[i];
     }
   };
 
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const int fr = lane & 15, fk = lane >> 4;
-  d4 c1[2][2], c2[2][2];
+  const int wr = 16 * wave;
+  d4 c1[CB], c2[CB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      c1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      c2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-
+  for (int j = 0; j < CB; ++j) {
+    c1[j] = d4{0.0, 0.0, 0.0, 0.0};
+    c2[j] = d4{0.0, 0.0, 0.0, 0.0};
+  }
   const int nsteps = a.Qp / BK;
+  __syncthreads();   // the LDS may still be read by the previous item
   load(0);
   store(0);
   __syncthreads();
@@ -118,27 +111,15 @@ __global__ __launch_bounds__(NT) void slab_f64_kernel(SlabArgs a) {
     if (step + 1 < nsteps) load((step + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double x1[2], y1[2];
+      const double x1 = A1[buf][kk + fk][wr + fr];
+      const double x2 = A2[buf][kk + fk][wr + fr];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) x1[i] = A1[buf][kk + fk][wm + 16 * i + fr];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) y1[j] = B1[buf][kk + fk][wn + 16 * j + fr];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          c1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[i], y1[j], c1[i][j], 0, 0, 0);
-      if (!diag) {
-        double x2[2], y2[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) x2[i] = A2[buf][kk + fk][wm + 16 * i + fr];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) y2[j] = B2[buf][kk + fk][wn + 16 * j + fr];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            c2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x2[i], y2[j], c2[i][j], 0, 0, 0);
+      for (int j = 0; j < CB; ++j) {
+        c1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, B1[buf][kk + fk][16 * j + fr], c1[j],
+                                                     0, 0, 0);
+        if (!diag)
+          c2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, B2[buf][kk + fk][16 * j + fr],
+                                                       c2[j], 0, 0, 0);
       }
     }
     if (step + 1 < nsteps) store(buf ^ 1);
@@ -149,24 +130,22 @@ __global__ __launch_bounds__(NT) void slab_f64_kernel(SlabArgs a) {
   const double cp = 0.70710678118654752440;   // sqrt(1/2)
   const double cm = 1.22474487139158904910;   // sqrt(3/2)
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < CB; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int x = x0 + wm + 16 * i + fk + 4 * r;
-        const int c = c0 + wn + 16 * j + fr;
-        if (x >= a.N || c >= a.nc) continue;
-        double* z = a.Z + (long)x * a.ldz + col0 + c;
-        if (diag) {
-          z[0] = c1[i][j][r];
-        } else {
-          const double u = c1[i][j][r], v = c2[i][j][r];
-          z[0] = cp * (u + v);
-          z[a.nc] = cm * (u - v);
-        }
+    for (int r = 0; r < 4; ++r) {
+      const int x = x0 + wr + fk + 4 * r;
+      const int c = c0 + 16 * j + fr;
+      if (x >= a.N || c >= a.nc) continue;
+      double* z = a.Z + (long)x * a.ldz + col0 + c;
+      if (diag) {
+        z[0] = c1[j][r];
+      } else {
+        const double u = c1[j][r], v = c2[j][r];
+        z[0] = cp * (u + v);
+        z[a.nc] = cm * (u - v);
       }
-  if (xt == 0 && tid < TB) {
+    }
+  if (xt == 0 && tid < TC) {
     const int c = c0 + tid;
     if (c < a.nc) {
       const double wgt = a.ep[p] + a.ep[q] - a.ec[c];
@@ -176,23 +155,42 @@ __global__ __launch_bounds__(NT) void slab_f64_kernel(SlabArgs a) {
   }
 }
 
-struct SyrkArgs {
-  const double* Z; long ldz; const double* w;
-  int N; long K; long kper;
-  double* part; long part_stride;   // per split: [2][N][N]
-  int tiles;                        // lower-triangle tile count
-};
+template <int TC>
+__global__ __launch_bounds__(NT) void slab_f64_kernel(SlabF64 a) {
+  __shared__ double A1[2][BK][LD], A2[2][BK][LD], B1[2][BK][LD], B2[2][BK][LD];
+  const long G = (long)a.npairs * a.tiles_x * a.tiles_c;
+  slab_tile<TC>(a, xcd_remap(blockIdx.x, G), A1, A2, B1, B2);
+}
 
-__global__ __launch_bounds__(NT) void syrk_f64_kernel(SyrkArgs a) {
-  __shared__ double X[2][BK][LD], Y[2][BK][LD], W[2][BK];
+// Job owning global work index `it`: the largest j with prefix[j] <= it
+// (jobs with no work share their prefix with the next job and are skipped).
+__device__ __forceinline__ int find_job(const long* prefix, int njobs, long it) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= it) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int TC>
+__global__ __launch_bounds__(NT) void slab_f64_grouped(const SlabF64* jobs, const long* prefix,
+                                                       int njobs, long total) {
+  __shared__ double A1[2][BK][LD], A2[2][BK][LD], B1[2][BK][LD], B2[2][BK][LD];
+  for (long it = blockIdx.x; it < total; it += gridDim.x) {
+    const int j = find_job(prefix, njobs, it);
+    slab_tile<TC>(jobs[j], it - prefix[j], A1, A2, B1, B2);
+  }
+}
+
+// One SYRK tile: lower-triangle tile t, K split s.
+__device__ void syrk_tile(const SyrkF64& a, int t, int s, double (*X)[BK][LD],
+                          double (*Y)[BK][LD], double (*W)[BK]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // tile -> (xt >= yt)
-  const int t = blockIdx.x;
   int xt = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((xt + 1) * (xt + 2) / 2 <= t) ++xt;
   while (xt * (xt + 1) / 2 > t) --xt;
   const int yt = t - xt * (xt + 1) / 2;
-  const int s = blockIdx.y;
   const long k0 = (long)s * a.kper, k1 = std::min(a.K, k0 + a.kper);
   const int x0 = xt * TB, y0 = yt * TB;
   const int lk = tid & 15, lr = tid >> 4;
@@ -227,11 +225,11 @@ __global__ __launch_bounds__(NT) void syrk_f64_kernel(SyrkArgs a) {
       u1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
   const long nsteps = (k1 > k0) ? (k1 - k0 + BK - 1) / BK : 0;
-  if (nsteps > 0) {
-    load(k0);
-    store(0);
-    __syncthreads();
-  }
+  if (nsteps == 0) return;   // uniform over the workgroup
+  __syncthreads();           // the LDS may still be read by the previous item
+  load(k0);
+  store(0);
+  __syncthreads();
   for (long step = 0; step < nsteps; ++step) {
     const int buf = step & 1;
     if (step + 1 < nsteps) load(k0 + (step + 1) * BK);
@@ -257,7 +255,6 @@ __global__ __launch_bounds__(NT) void syrk_f64_kernel(SyrkArgs a) {
     if (step + 1 < nsteps) store(buf ^ 1);
     __syncthreads();
   }
-  if (nsteps == 0) return;
   double* P0 = a.part + (long)s * a.part_stride;
   double* P1 = P0 + (long)a.N * a.N;
 #pragma unroll
@@ -273,6 +270,22 @@ __global__ __launch_bounds__(NT) void syrk_f64_kernel(SyrkArgs a) {
         P0[o] += u0[i][j][r];
         P1[o] += u1[i][j][r];
       }
+}
+
+__global__ __launch_bounds__(NT) void syrk_f64_kernel(SyrkF64 a) {
+  __shared__ double X[2][BK][LD], Y[2][BK][LD], W[2][BK];
+  syrk_tile(a, blockIdx.x, blockIdx.y, X, Y, W);
+}
+
+__global__ __launch_bounds__(NT) void syrk_f64_grouped(const SyrkF64* jobs, const long* prefix,
+                                                       int njobs, long total) {
+  __shared__ double X[2][BK][LD], Y[2][BK][LD], W[2][BK];
+  for (long it = blockIdx.x; it < total; it += gridDim.x) {
+    const int j = find_job(prefix, njobs, it);
+    const SyrkF64& a = jobs[j];
+    const long l = it - prefix[j];
+    syrk_tile(a, (int)(l % a.tiles), (int)(l / a.tiles), X, Y, W);
+  }
 }
 
 // U[x][y] = U[y][x] = sum_s part[s][m][x][y] for x >= y (fixed order).
@@ -293,13 +306,76 @@ __global__ void reduce_sym_kernel(const double* part, long part_stride, int nspl
   }
 }
 
+__global__ void fill_zero_kernel(double* p, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+inline long nblocks(long n) { return std::max<long>(1, std::min<long>((n + 255) / 256, 4096)); }
+
 }  // namespace
+
+int slab_f64_tc(int nc) { return nc >= 48 ? 64 : (nc >= 24 ? 32 : 16); }
+
+long slab_f64_tiles(const SlabF64& a) { return (long)a.npairs * a.tiles_x * a.tiles_c; }
+
+void launch_slab_f64(int tc, const SlabF64& a, hipStream_t st) {
+  const dim3 grid((unsigned)slab_f64_tiles(a));
+  if (tc == 16) hipLaunchKernelGGL(slab_f64_kernel<16>, grid, dim3(NT), 0, st, a);
+  else if (tc == 32) hipLaunchKernelGGL(slab_f64_kernel<32>, grid, dim3(NT), 0, st, a);
+  else hipLaunchKernelGGL(slab_f64_kernel<64>, grid, dim3(NT), 0, st, a);
+  AGF2_CHECK_LAUNCH();
+}
+
+void launch_syrk_f64(const SyrkF64& a, hipStream_t st) {
+  hipLaunchKernelGGL(syrk_f64_kernel, dim3(a.tiles, a.nsplit), dim3(NT), 0, st, a);
+  AGF2_CHECK_LAUNCH();
+}
+
+void launch_slab_f64_grouped(int tc, const SlabF64* jobs, const long* prefix, int njobs,
+                             long total, int grid, hipStream_t st) {
+  if (total <= 0 || njobs <= 0) return;
+  const dim3 g((unsigned)std::max<long>(1, std::min<long>(grid, total)));
+  if (tc == 16) hipLaunchKernelGGL(slab_f64_grouped<16>, g, dim3(NT), 0, st, jobs, prefix, njobs, total);
+  else if (tc == 32) hipLaunchKernelGGL(slab_f64_grouped<32>, g, dim3(NT), 0, st, jobs, prefix, njobs, total);
+  else hipLaunchKernelGGL(slab_f64_grouped<64>, g, dim3(NT), 0, st, jobs, prefix, njobs, total);
+  AGF2_CHECK_LAUNCH();
+}
+
+void launch_syrk_f64_grouped(const SyrkF64* jobs, const long* prefix, int njobs, long total,
+                             int grid, hipStream_t st) {
+  if (total <= 0 || njobs <= 0) return;
+  const dim3 g((unsigned)std::max<long>(1, std::min<long>(grid, total)));
+  hipLaunchKernelGGL(syrk_f64_grouped, g, dim3(NT), 0, st, jobs, prefix, njobs, total);
+  AGF2_CHECK_LAUNCH();
+}
+
+int grouped_grid_f64(int kind, int tc) {
+  static int cached[4] = {0, 0, 0, 0};   // slab 16/32/64, syrk (one device type per process)
+  const int slot = kind == 1 ? 3 : (tc == 16 ? 0 : tc == 32 ? 1 : 2);
+  if (cached[slot] > 0) return cached[slot];
+  int dev = 0, cus = 0, per = 0;
+  AGF2_HIP(hipGetDevice(&dev));
+  AGF2_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (slot == 0) AGF2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, slab_f64_grouped<16>, NT, 0));
+  else if (slot == 1) AGF2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, slab_f64_grouped<32>, NT, 0));
+  else if (slot == 2) AGF2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, slab_f64_grouped<64>, NT, 0));
+  else AGF2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, syrk_f64_grouped, NT, 0));
+  cached[slot] = std::max(1, cus) * std::max(1, per);
+  return cached[slot];
+}
+
+void fill_zero(double* p, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(nblocks(n)), dim3(256), 0, st, p, n);
+  AGF2_CHECK_LAUNCH();
+}
 
 void reduce_moment_partials(const double* part, long part_stride, int nsplit, int N,
                             double* U0, double* U1, hipStream_t st) {
   const long nn = (long)N * N;
-  const long blocks = std::min<long>((nn + 255) / 256, 4096);
-  hipLaunchKernelGGL(reduce_sym_kernel, dim3(blocks), dim3(256), 0, st, part, part_stride,
+  hipLaunchKernelGGL(reduce_sym_kernel, dim3(nblocks(nn)), dim3(256), 0, st, part, part_stride,
                      nsplit, N, U0, U1);
   AGF2_CHECK_LAUNCH();
 }
@@ -323,34 +399,36 @@ PairTable make_pairs(int np, int nc) {
   return t;
 }
 
-}  // namespace
-
-static long ndiag(const PairTable& t, int P0, int P1) {
+long ndiag(const PairTable& t, int P0, int P1) {
   long n = 0;
   for (int P = P0; P < P1; ++P) n += (t.pi[P] == t.pj[P]);
   return n;
 }
 
+}  // namespace
+
 // One part (lesser or greater) of the moment build.
 static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, long sRp,
                              long sRx, const double* S, long sSp, long sSc,
                              const double* ep, int np, const double* ec, int nc,
-                             double* U0, double* U1, int slot) {
+                             double* U0, double* U1) {
   hipStream_t st = h.stream;
   const long nn = (long)N * N;
   if (np == 0 || nc == 0) {
-    AGF2_HIP(hipMemsetAsync(U0, 0, nn * sizeof(double), st));
-    AGF2_HIP(hipMemsetAsync(U1, 0, nn * sizeof(double), st));
+    fill_zero(U0, nn, st);
+    fill_zero(U1, nn, st);
     return;
   }
   PairTable t = make_pairs(np, nc);
   const int npairs = (int)t.pi.size();
-  int* d_pi = h.ws_moments[slot].as<int>(2L * npairs + 2 * (npairs + 1));
+  int* d_pi = h.ws_moments[6].as<int>(2L * npairs);
   int* d_pj = d_pi + npairs;
-  long* d_col = reinterpret_cast<long*>(h.ws_moments[slot + 1].get((npairs + 1) * sizeof(long)));
+  long* d_col = h.ws_moments[7].as<long>(npairs + 1);
   AGF2_HIP(hipMemcpyAsync(d_pi, t.pi.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
   AGF2_HIP(hipMemcpyAsync(d_pj, t.pj.data(), npairs * sizeof(int), hipMemcpyHostToDevice, st));
-  AGF2_HIP(hipMemcpyAsync(d_col, t.col.data(), (npairs + 1) * sizeof(long), hipMemcpyHostToDevice, st));
+  AGF2_HIP(hipMemcpyAsync(d_col, t.col.data(), (npairs + 1) * sizeof(long),
+                          hipMemcpyHostToDevice, st));
+  AGF2_HIP(hipStreamSynchronize(st));   // host tables go out of scope below
 
   // Z chunk capacity: whole pairs, at most ~1 GiB of Z
   const long cap_bytes = 1L << 30;
@@ -365,9 +443,9 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
   const int nsplit_max = std::max(1, std::min(64, (2048 + nlower - 1) / nlower));
   const long part_stride = 2 * nn;
   double* part = h.ws_moments[5].as<double>(part_stride * nsplit_max);
-  AGF2_HIP(hipMemsetAsync(part, 0, part_stride * nsplit_max * sizeof(double), st));
+  fill_zero(part, part_stride * nsplit_max, st);
 
-  const int tiles_x = tiles_n, tiles_c = (nc + TB - 1) / TB;
+  const int tc = slab_f64_tc(nc);
   int P0 = 0;
   while (P0 < npairs) {
     int P1 = P0;
@@ -375,36 +453,33 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
     if (P1 == P0) P1 = P0 + 1;
     const long Kc = t.col[P1] - t.col[P0];
 
-    SlabArgs sa;
+    SlabF64 sa;
     sa.R = R; sa.sRp = sRp; sa.sRx = sRx;
     sa.S = S; sa.sSp = sSp; sa.sSc = sSc;
     sa.ep = ep; sa.ec = ec; sa.N = N; sa.nc = nc; sa.Qp = Qp;
     sa.pi = d_pi; sa.pj = d_pj; sa.pcol = d_col;
     sa.pair0 = P0; sa.npairs = P1 - P0; sa.col_base = t.col[P0];
     sa.Z = Z; sa.ldz = kcap; sa.w = w;
-    sa.tiles_x = tiles_x; sa.tiles_c = tiles_c;
-    const long G = (long)sa.npairs * tiles_x * tiles_c;
+    sa.tiles_x = tiles_n; sa.tiles_c = (nc + tc - 1) / tc;
     {
       // algorithmic: 2 N nc Q per (p,q) slab, two slabs per off-diagonal pair;
       // bytes: the Z chunk and its weights written once
       const double slabs = (double)(2 * (P1 - P0)) - (double)ndiag(t, P0, P1);
       ProfScope ps(h, "moments.slab", slabs * 2.0 * N * nc * Q, 8.0 * (N + 1.0) * Kc);
-      hipLaunchKernelGGL(slab_f64_kernel, dim3((unsigned)G), dim3(NT), 0, st, sa);
-      AGF2_CHECK_LAUNCH();
+      launch_slab_f64(tc, sa, st);
     }
 
     int nsplit = (int)std::min<long>(nsplit_max, std::max<long>(1, Kc / 256));
     long kper = (Kc + nsplit - 1) / nsplit;
     kper = (kper + BK - 1) / BK * BK;
     nsplit = (int)((Kc + kper - 1) / kper);
-    SyrkArgs ya;
-    ya.Z = Z; ya.ldz = kcap; ya.w = w; ya.N = N; ya.K = Kc; ya.kper = kper;
+    SyrkF64 ya;
+    ya.Z = Z; ya.ldz = kcap; ya.w = w; ya.N = N; ya.K = Kc; ya.kper = kper; ya.nsplit = nsplit;
     ya.part = part; ya.part_stride = part_stride; ya.tiles = nlower;
     {
       // algorithmic: lower triangles of two symmetric N x N products over Kc
       ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 1.0) * Kc);
-      hipLaunchKernelGGL(syrk_f64_kernel, dim3(nlower, nsplit), dim3(NT), 0, st, ya);
-      AGF2_CHECK_LAUNCH();
+      launch_syrk_f64(ya, st);
     }
     P0 = P1;
   }
@@ -425,6 +500,18 @@ void pole_transform_f64(Handle& h, int N, int Q, int Qp, const double* L,
   gemm_f64_padded(g, Qp, h.stream);
 }
 
+// Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q]
+void lov_transform_f64(int N, int Q, int Qp, const double* u, int npole, int o, int v,
+                       const double* Lxv, double* Lov, hipStream_t st) {
+  if (o == 0 || v == 0) return;
+  Gemm g;
+  g.M = o; g.N = Q; g.K = N; g.batch = v;
+  g.A = u; g.sAm = 1; g.sAk = npole;
+  g.B = Lxv; g.sBb = (long)N * Qp; g.sBk = Qp; g.sBn = 1;
+  g.C = Lov; g.sCb = Qp; g.sCm = (long)v * Qp; g.sCn = 1;
+  gemm_f64_padded(g, Qp, st);
+}
+
 void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
                        int nocc, const double* e, const double* u, double* m0o,
                        double* m1o, double* m0v, double* m1v) {
@@ -434,27 +521,19 @@ void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
   double* Lxv = h.ws_moments[1].as<double>((long)v * N * Qp);
   double* Lov = h.ws_moments[2].as<double>((long)o * v * Qp);
   {
-  ProfScope ps(h, "moments.transform",
-               2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
-               8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
-  pole_transform_f64(h, N, Q, Qp, L, u, npole, 0, o, Lxo);
-  pole_transform_f64(h, N, Q, Qp, L, u, npole, o, v, Lxv);
-  // Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q]
-  {
-    Gemm g;
-    g.M = o; g.N = Q; g.K = N; g.batch = v;
-    g.A = u; g.sAm = 1; g.sAk = npole;
-    g.B = Lxv; g.sBb = (long)N * Qp; g.sBk = Qp; g.sBn = 1;
-    g.C = Lov; g.sCb = Qp; g.sCm = (long)v * Qp; g.sCn = 1;
-    gemm_f64_padded(g, Qp, h.stream);
-  }
+    ProfScope ps(h, "moments.transform",
+                 2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
+                 8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
+    pole_transform_f64(h, N, Q, Qp, L, u, npole, 0, o, Lxo);
+    pole_transform_f64(h, N, Q, Qp, L, u, npole, o, v, Lxv);
+    lov_transform_f64(N, Q, Qp, u, npole, o, v, Lxv, Lov, h.stream);
   }
   // lesser: pairs (i, j) occupied, inner a virtual; S[j][a][Q] = Lov[j][a][Q]
   moments_part_f64(h, N, Q, Qp, Lxo, (long)N * Qp, Qp, Lov, (long)v * Qp, Qp,
-                   e, o, e + o, v, m0o, m1o, 6);
+                   e, o, e + o, v, m0o, m1o);
   // greater: pairs (a, b) virtual, inner i occupied; S[b][i][Q] = Lov[i][b][Q]
   moments_part_f64(h, N, Q, Qp, Lxv, (long)N * Qp, Qp, Lov, Qp, (long)v * Qp,
-                   e + o, v, e, o, m0v, m1v, 6);
+                   e + o, v, e, o, m0v, m1v);
 }
 
 }  // namespace agf2

@@ -94,3 +94,20 @@ SMALL = dict(nmo=24, nocc=5, naux=80)          # oracle runs to convergence in s
 MEDIUM = dict(nmo=200, nocc=40, naux=700)      # double-zeta-molecule-like
 LARGE = dict(nmo=1000, nocc=76, naux=3500)     # ~1000 orbitals, artemisinin-like nocc
 EVAL400 = dict(nmo=400, nocc=80, naux=1400)    # warm-start evaluation size
+
+
+def batch_shapes(nsys: int = 64, seed0: int = 1000, nmo_lo: int = 40, nmo_hi: int = 160):
+    """Shapes of a batch of systems of uneven size: a list of dicts with seed
+    (seed0 + k), nmo uniform over the integers [nmo_lo, nmo_hi] (PCG64 keyed
+    by (seed0, 3)), nocc = nmo / 5 rounded half up and naux = 3.5 nmo rounded
+    half up."""
+    rng = np.random.Generator(np.random.PCG64([seed0, 3]))
+    nmo = rng.integers(nmo_lo, nmo_hi, endpoint=True, size=nsys)
+    out = []
+    for k, n in enumerate(nmo.tolist()):
+        out.append(dict(seed=seed0 + k, nmo=n, nocc=max(1, int(np.floor(n / 5 + 0.5))),
+                        naux=int(np.floor(3.5 * n + 0.5))))
+    return out
+
+
+BATCH64 = dict(nsys=64, seed0=1000, nmo_lo=40, nmo_hi=160)   # batched moment build
