@@ -111,3 +111,23 @@ def batch_shapes(nsys: int = 64, seed0: int = 1000, nmo_lo: int = 40, nmo_hi: in
 
 
 BATCH64 = dict(nsys=64, seed0=1000, nmo_lo=40, nmo_hi=160)   # batched moment build
+
+
+MLP_SHAPES = [(12, 256), (256,), (256, 256), (256,), (256, 20), (20,)]   # W1 b1 W2 b2 W3 b3
+
+
+def mlp_init(seed: int, out_scale: float = 0.1) -> np.ndarray:
+    """Initial parameters of the warm-start network, flat float32 in the
+    order W1, b1, W2, b2, W3, b3 (weights [fan_in, fan_out], row-major):
+    weights normal with variance 2 / fan_in (the last layer's scaled by
+    out_scale so the first predictions are small), biases zero. PCG64 keyed
+    by (seed, 4)."""
+    rng = np.random.Generator(np.random.PCG64([seed, 4]))
+    parts = []
+    for k, shape in enumerate(MLP_SHAPES):
+        if len(shape) == 1:
+            parts.append(np.zeros(shape))
+        else:
+            w = rng.standard_normal(shape) * np.sqrt(2.0 / shape[0])
+            parts.append(w * (out_scale if k == len(MLP_SHAPES) - 2 else 1.0))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
