@@ -308,6 +308,93 @@ agf2_status agf2_profile_get(agf2_handle_t handle, int idx, const char** name,
                              long* launches, double* ms, double* flops,
                              double* bytes);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method: a predictor that moves
+ * the iteration-0 moments towards the converged ones so that the
+ * self-consistent loop of agf2_run starts closer to its fixed point; the
+ * fixed point itself is unchanged, and agf2_run falls back to the cold start
+ * when the corrected moments cannot be compressed).
+ *
+ * A per-orbital network of three linear maps (12 -> 256 -> 256 -> 20) with
+ * GELU (z Phi(z), Phi the normal distribution function) after the first
+ * two. The products run on FP16 MFMA with FP32 accumulation: features,
+ * hidden activations and weights are rounded to IEEE half precision as
+ * operands; pre-activations, biases and outputs are float32. Training
+ * (backward pass, Adam) runs in float32 on FP32 master parameters.
+ *
+ * Features of physical orbital x (float32 [N][12]), from the mean-field
+ * energies e and the iteration-0 moments U_n (n = 0<, 1<, 0>, 1>):
+ *   e_x, e_x - mu0 (mu0 = (e_HOMO + e_LUMO)/2), e_LUMO - e_HOMO,
+ *   +1 occupied / -1 virtual, U_n[x][x] / s_n (4), log s_n (4),
+ * with s_n the mean |diagonal| of U_n (at least 1e-30).
+ * Outputs (float32 [N][20]): for moment n, y[5n] = r_n(x) and
+ * y[5n+1..5n+4] = W_n(x, 0..3); the correction is
+ *   Delta U_n = s_n (diag(r_n) + W_n diag(1, 1, -1, -1) W_n^T).
+ * Loss of one system, T_n = (U_n(converged) - U_n(iteration 0)) / s_n:
+ *   sum_n || diag(r_n) + W_n S W_n^T - T_n ||_F^2 / N.
+ *
+ * Parameters: float32, flat, in the order W1 [12][256], b1 [256],
+ * W2 [256][256], b2 [256], W3 [256][20], b3 [20] (weights [in][out]).
+ * ---------------------------------------------------------------------- */
+#define AGF2_MLP_FEATURES 12
+#define AGF2_MLP_HIDDEN 256
+#define AGF2_MLP_OUTPUTS 20
+#define AGF2_MLP_NPARAM 74260
+
+typedef struct agf2_mlp_s* agf2_mlp_t;
+
+/* Create a network on the handle's device (parameters zero, Adam state
+ * empty) / free it. A network is used with handles of its device only. */
+agf2_status agf2_mlp_create(agf2_handle_t handle, agf2_mlp_t* net);
+agf2_status agf2_mlp_destroy(agf2_mlp_t net);
+
+/* Copy parameters in from / out to host float32 [AGF2_MLP_NPARAM]. Setting
+ * parameters resets the Adam state. agf2_mlp_get_grad copies out the
+ * gradient left by the last agf2_mlp_backward. */
+agf2_status agf2_mlp_set_params(agf2_handle_t handle, agf2_mlp_t net, const float* params);
+agf2_status agf2_mlp_get_params(agf2_handle_t handle, agf2_mlp_t net, float* params);
+agf2_status agf2_mlp_get_grad(agf2_handle_t handle, agf2_mlp_t net, float* grad);
+
+/* Features of one system. e_mf device [nphys]; m0 device [4][nphys][nphys]
+ * (U0<, U1<, U0>, U1> at iteration 0); X device float32 [nphys][12] and
+ * scale device float64 [4] (s_n) outputs. Needs 1 <= nocc < nphys. */
+agf2_status agf2_mlp_features(agf2_handle_t handle, int nphys, int nocc, const double* e_mf,
+                              const double* m0, float* X, double* scale);
+
+/* Y = network(X) for `rows` orbitals (any number of systems stacked).
+ * X device float32 [rows][12]; Y device float32 [rows][20]. The network
+ * keeps this call's activations for the next agf2_mlp_backward. */
+agf2_status agf2_mlp_forward(agf2_handle_t handle, agf2_mlp_t net, int rows, const float* X,
+                             float* Y);
+
+/* Loss of one system and its gradient with respect to that system's
+ * outputs. Y device float32 [nphys][20]; m0, mconv device [4][nphys][nphys]
+ * (iteration-0 and converged moments); scale device [4] from
+ * agf2_mlp_features; dY device float32 [nphys][20] output; loss device
+ * float64 scalar, incremented by this system's loss. */
+agf2_status agf2_mlp_loss_grad(agf2_handle_t handle, int nphys, const float* Y,
+                               const double* m0, const double* mconv, const double* scale,
+                               float* dY, double* loss);
+
+/* Gradient of sum(Y * dY) with respect to the parameters, through the
+ * activations of the last agf2_mlp_forward (same rows); overwrites the
+ * network's gradient. dY device float32 [rows][20]. */
+agf2_status agf2_mlp_backward(agf2_handle_t handle, agf2_mlp_t net, int rows, const float* dY);
+
+/* One Adam step (Kingma and Ba; bias-corrected moments, step count kept by
+ * the network) on the FP32 master parameters with the current gradient;
+ * refreshes the FP16 copies used by the forward pass. */
+agf2_status agf2_mlp_adam_step(agf2_handle_t handle, agf2_mlp_t net, float lr, float beta1,
+                               float beta2, float eps);
+
+/* Warm-start correction of one system: features, forward pass and
+ * Delta U_n as above. e_mf device [nphys]; m0 device [4][nphys][nphys]
+ * (iteration-0 moments); dm device [4][nphys][nphys] output, suitable as
+ * agf2_run's dm_init. */
+agf2_status agf2_mlp_predict_correction(agf2_handle_t handle, agf2_mlp_t net, int nphys,
+                                        int nocc, const double* e_mf, const double* m0,
+                                        double* dm);
+
 #ifdef __cplusplus
 }
 #endif

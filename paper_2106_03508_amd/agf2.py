@@ -73,6 +73,18 @@ SIGNATURES = {
     "agf2_run_opts_default": (None, [ctypes.POINTER(RunOpts)]),
     "agf2_run": (_I, [_P, ctypes.POINTER(RunOpts), _I, _I, _P, _P, _P, _I, _P,
                       ctypes.POINTER(IterRecord), _IP, _IP, _P, _P, _IP, _P]),
+    "agf2_mlp_create": (_I, [_P, ctypes.POINTER(_P)]),
+    "agf2_mlp_destroy": (_I, [_P]),
+    "agf2_mlp_set_params": (_I, [_P, _P, _P]),
+    "agf2_mlp_get_params": (_I, [_P, _P, _P]),
+    "agf2_mlp_get_grad": (_I, [_P, _P, _P]),
+    "agf2_mlp_features": (_I, [_P, _I, _I, _P, _P, _P, _P]),
+    "agf2_mlp_forward": (_I, [_P, _P, _I, _P, _P]),
+    "agf2_mlp_loss_grad": (_I, [_P, _I, _P, _P, _P, _P, _P, _P]),
+    "agf2_mlp_backward": (_I, [_P, _P, _I, _P]),
+    "agf2_mlp_adam_step": (_I, [_P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float]),
+    "agf2_mlp_predict_correction": (_I, [_P, _P, _I, _I, _P, _P, _P]),
     "agf2_profile_enable": (_I, [_P, _I]),
     "agf2_profile_count": (_I, [_P]),
     "agf2_profile_get": (_I, [_P, _I, ctypes.POINTER(ctypes.c_char_p),
@@ -109,6 +121,18 @@ def _ptr(t: torch.Tensor, name: str, dev: torch.device) -> int:
         raise TypeError(f"{name} must be a torch tensor")
     if t.dtype != torch.float64:
         raise TypeError(f"{name} must be float64")
+    if t.device != dev:
+        raise ValueError(f"{name} must be on {dev}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _ptr32(t: torch.Tensor, name: str, dev: torch.device) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
     if t.device != dev:
         raise ValueError(f"{name} must be on {dev}")
     if not t.is_contiguous():
@@ -342,3 +366,103 @@ def agf2_run(h: Handle, L, hcore, e_mf, nocc: int, opts: RunOpts = None, dm_init
     return dict(history=history, converged=bool(conv.value), e_pole=e_pole[:npole],
                 u_pole=u_pole.view(-1)[:nphys * npole].view(nphys, npole),
                 nocc_pole=nocc_pole.value, rdm1=rdm1)
+
+
+# ---------------------------------------------------------------- warm start
+MLP_FEATURES, MLP_HIDDEN, MLP_OUTPUTS, MLP_NPARAM = 12, 256, 20, 74260
+
+
+class Mlp:
+    """A warm-start network on the handle's device (see agf2_mlp_* in the
+    header). Parameters move in and out as float32 numpy arrays."""
+
+    def __init__(self, h: Handle, params=None):
+        self.h = h
+        p = _P()
+        h._check(h.lib.agf2_mlp_create(h.h, ctypes.byref(p)))
+        self.p = p
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, params):
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.shape != (MLP_NPARAM,):
+            raise ValueError(f"parameters must have shape ({MLP_NPARAM},)")
+        self.h._check(self.h.lib.agf2_mlp_set_params(self.h.h, self.p, a.ctypes.data))
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(MLP_NPARAM, dtype=np.float32)
+        self.h._check(self.h.lib.agf2_mlp_get_params(self.h.h, self.p, a.ctypes.data))
+        return a
+
+    def get_grad(self):
+        import numpy as np
+        a = np.empty(MLP_NPARAM, dtype=np.float32)
+        self.h._check(self.h.lib.agf2_mlp_get_grad(self.h.h, self.p, a.ctypes.data))
+        return a
+
+    def close(self):
+        if getattr(self, "p", None):
+            self.h.lib.agf2_mlp_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def agf2_mlp_features(h: Handle, e_mf, nocc: int, m0):
+    """(X float32 [N, 12], scale float64 [4]) of one system; m0 [4, N, N]."""
+    N = e_mf.shape[0]
+    X = torch.empty(N, MLP_FEATURES, dtype=torch.float32, device=h.device)
+    s = h.empty(4)
+    h._check(h.lib.agf2_mlp_features(h.h, N, nocc, _ptr(e_mf, "e_mf", h.device),
+                                     _ptr(m0, "m0", h.device), _ptr32(X, "X", h.device),
+                                     _ptr(s, "scale", h.device)))
+    return X, s
+
+
+def agf2_mlp_forward(h: Handle, net: Mlp, X, Y=None):
+    rows = X.shape[0]
+    if Y is None:
+        Y = torch.empty(rows, MLP_OUTPUTS, dtype=torch.float32, device=h.device)
+    h._check(h.lib.agf2_mlp_forward(h.h, net.p, rows, _ptr32(X, "X", h.device),
+                                    _ptr32(Y, "Y", h.device)))
+    return Y
+
+
+def agf2_mlp_loss_grad(h: Handle, Y, m0, mconv, scale, dY=None, loss=None):
+    """dY of one system; adds its loss into the device scalar `loss`."""
+    N = Y.shape[0]
+    if dY is None:
+        dY = torch.empty_like(Y)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=h.device)
+    h._check(h.lib.agf2_mlp_loss_grad(h.h, N, _ptr32(Y, "Y", h.device),
+                                      _ptr(m0, "m0", h.device), _ptr(mconv, "mconv", h.device),
+                                      _ptr(scale, "scale", h.device), _ptr32(dY, "dY", h.device),
+                                      _ptr(loss, "loss", h.device)))
+    return dY, loss
+
+
+def agf2_mlp_backward(h: Handle, net: Mlp, dY):
+    h._check(h.lib.agf2_mlp_backward(h.h, net.p, dY.shape[0], _ptr32(dY, "dY", h.device)))
+
+
+def agf2_mlp_adam_step(h: Handle, net: Mlp, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    h._check(h.lib.agf2_mlp_adam_step(h.h, net.p, lr, beta1, beta2, eps))
+
+
+def agf2_mlp_predict_correction(h: Handle, net: Mlp, e_mf, nocc: int, m0, out=None):
+    """Delta U [4, N, N] for agf2_run's dm_init."""
+    N = e_mf.shape[0]
+    if out is None:
+        out = h.empty(4, N, N)
+    h._check(h.lib.agf2_mlp_predict_correction(h.h, net.p, N, nocc, _ptr(e_mf, "e_mf", h.device),
+                                               _ptr(m0, "m0", h.device),
+                                               _ptr(out, "dm", h.device)))
+    return out

@@ -104,36 +104,6 @@ namespace {
                                             rocblas_status_to_string(s_)};  \
   } while (0)
 
-struct DeviceGuard {
-  int prev = 0;
-  explicit DeviceGuard(int dev) {
-    (void)hipGetDevice(&prev);
-    AGF2_HIP(hipSetDevice(dev));
-  }
-  ~DeviceGuard() { (void)hipSetDevice(prev); }
-};
-
-template <class F>
-agf2_status guarded(agf2_handle_t hh, F&& body) {
-  if (!hh) return AGF2_ERR_ARG;
-  Handle& h = *reinterpret_cast<Handle*>(hh);
-  try {
-    DeviceGuard g(h.device);
-    body(h);
-    h.last_error.clear();
-    return AGF2_OK;
-  } catch (const Error& e) {
-    h.last_error = e.msg;
-    return e.status;
-  } catch (const std::bad_alloc&) {
-    h.last_error = "host allocation failed";
-    return AGF2_ERR_NOMEM;
-  } catch (const std::exception& e) {
-    h.last_error = e.what();
-    return AGF2_ERR_HIP;
-  }
-}
-
 double* host_scratch(Handle& h, size_t n) {
   if (n > h.host_red_n) {
     if (h.host_red) AGF2_HIP(hipHostFree(h.host_red));

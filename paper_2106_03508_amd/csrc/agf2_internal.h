@@ -6,6 +6,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <map>
 #include <string>
 #include <vector>
@@ -191,6 +193,7 @@ struct Handle {
   DevBuf ws_fock[8];
   DevBuf ws_misc[8];
   DevBuf ws_run[8];
+  DevBuf ws_mlp[2];   // warm-start loss partials and prediction scratch
   DevBuf ws_red;
   double* host_red = nullptr;   // pinned scratch for small reductions
   size_t host_red_n = 0;
@@ -206,5 +209,38 @@ struct ProfScope {
   ProfScope(Handle& hh, const char* name, double flops, double bytes);
   ~ProfScope();
 };
+
+// Makes the handle's device current for a scope.
+struct DeviceGuard {
+  int prev = 0;
+  explicit DeviceGuard(int dev) {
+    (void)hipGetDevice(&prev);
+    AGF2_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+// Runs an entry point's body with the handle's device current and turns
+// exceptions into status codes (the message kept for agf2_last_error).
+template <class F>
+agf2_status guarded(agf2_handle_t hh, F&& body) {
+  if (!hh) return AGF2_ERR_ARG;
+  Handle& h = *reinterpret_cast<Handle*>(hh);
+  try {
+    DeviceGuard g(h.device);
+    body(h);
+    h.last_error.clear();
+    return AGF2_OK;
+  } catch (const Error& e) {
+    h.last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    h.last_error = "host allocation failed";
+    return AGF2_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    h.last_error = e.what();
+    return AGF2_ERR_HIP;
+  }
+}
 
 }  // namespace agf2
