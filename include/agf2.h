@@ -140,7 +140,7 @@ agf2_status agf2_compress(agf2_handle_t handle, int nphys, const double* m0,
 
 /* Options of the Fock loop. */
 typedef struct {
-  double tol_rdm1;    /* stop when the RMS change of the density is below   */
+  double tol_rdm1;    /* stop when ||change of the density||_F is below     */
   double tol_nelec;   /* |electron count - nelec| target of the shift fit   */
   double bracket;     /* largest shift step tried, Ha                        */
   double step0;       /* first shift step of the bracket search, Ha          */
@@ -160,7 +160,7 @@ void agf2_fock_opts_default(agf2_fock_opts* opts);
  * the aufbau count 2 * sum_{l<n} |u_l|^2 equals nelec, diagonalises
  *   [[F, v_se], [v_se^T, diag(e_se + Delta)]],
  * rebuilds rdm1 = 2 sum_{l<n} u_l u_l^T and F = F[rdm1] (DIIS on F), until
- * the RMS change of rdm1 is below tol_rdm1.
+ * the Frobenius norm of the change of rdm1 is below tol_rdm1.
  *   hcore      device [nphys][nphys]; Lpq device [naux][nphys][nphys]
  *   nelec      electrons (even, 0 < nelec < 2 * (nphys + naux_se))
  *   naux_se    auxiliaries; v_se device [nphys][naux_se] (row stride

@@ -448,8 +448,11 @@ def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
 
     Each cycle: Delta fitted at the current F; eigendecomposition of
     [[F, v], [v^T, diag(e + Delta)]]; aufbau; D = 2 sum_{l<n*} u_l u_l^T;
-    stop when the RMS change of D is below tol_rdm1, else the next F is
+    stop when the norm (Frobenius) of the change of D is below tol_rdm1, else
+    the next F is
     F[D], DIIS-extrapolated with the fixed-point residual F[D] - F as error.
+    Reading: the tolerance bounds the whole change of the density matrix, so
+    the energy it leaves unconverged does not grow with the basis size.
     The returned F is the one diagonalised last, so the returned poles are
     exact eigenpairs of the returned extended Hamiltonian.
     Returns a dict."""
@@ -467,7 +470,7 @@ def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
         n_eig += 1
         uo = u[:, :n]
         D_new = 2.0 * uo @ uo.T
-        err = np.sqrt(np.mean((D_new - D) ** 2))
+        err = np.linalg.norm(D_new - D)
         D = D_new
         if err < tol_rdm1:
             converged = True

@@ -539,10 +539,10 @@ FockLoopResult fock_loop_impl(Handle& h, int nphys, int naux, const double* Lpq,
     g.C = Dn; g.sCm = N; g.sCn = 1; g.alpha = 2.0;
     if (a.n > 0) gemm_f64(g, s);
     else AGF2_HIP(hipMemsetAsync(Dn, 0, nn * sizeof(double), s));
-    // RMS change of D
+    // Frobenius norm of the change of D
     hipLaunchKernelGGL(sqdiff_kernel, dim3(nblk(nn)), dim3(256), 0, s, nn, Dn, rdm1, Fn);
     AGF2_CHECK_LAUNCH();
-    const double err = std::sqrt(dot_f64(h, nn, Fn, Fn) / (double)nn);
+    const double err = std::sqrt(dot_f64(h, nn, Fn, Fn));
     AGF2_HIP(hipMemcpyAsync(rdm1, Dn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (err < o.tol_rdm1) { converged = true; break; }
     fock_build(h, N, naux, Lpq, hcore, rdm1, 1.0, Fn);
