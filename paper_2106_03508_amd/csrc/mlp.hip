@@ -31,7 +31,7 @@ typedef h16 h16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int NF = AGF2_MLP_FEATURES, NFP = 32, NH = AGF2_MLP_HIDDEN, NO = AGF2_MLP_OUTPUTS,
-              NOP = 32, RANK = 4, NMOM = 4;
+              NOP = 32, NMOM = 4;
 constexpr long OW1 = 0, OB1 = OW1 + (long)NF * NH, OW2 = OB1 + NH, OB2 = OW2 + (long)NH * NH,
                OW3 = OB2 + NH, OB3 = OW3 + (long)NH * NO, NPARAM = OB3 + NO;
 static_assert(NPARAM == AGF2_MLP_NPARAM, "parameter count");
@@ -173,8 +173,8 @@ __global__ void col_sums(int M, int N, const float* __restrict__ D, float* __res
 }
 
 // One workgroup per (orbital x, moment n): row x of the residual
-// R = diag(r) + W S W^T - (mconv - m0) / s, its squared norm, and the
-// gradient dY[x][5n .. 5n+4].
+// R = diag(r_n) + sum_m (c_nm(x) + c_nm(y)) U_m / s_m - (mconv - m0)_n / s_n,
+// its squared norm, and the gradient dY[x][5n .. 5n+4].
 __global__ __launch_bounds__(256) void head_loss(int N, const float* __restrict__ Y,
                                                  const double* __restrict__ m0,
                                                  const double* __restrict__ mc,
@@ -182,47 +182,48 @@ __global__ __launch_bounds__(256) void head_loss(int N, const float* __restrict_
                                                  float* __restrict__ dY,
                                                  double* __restrict__ lpart) {
   const int x = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
-  const double sg[RANK] = {1.0, 1.0, -1.0, -1.0};
-  double wx[RANK];
+  const long nn = (long)N * N;
+  double cx[NMOM], inv_s[NMOM];
 #pragma unroll
-  for (int k = 0; k < RANK; ++k) wx[k] = Y[(long)x * NO + 5 * n + 1 + k];
+  for (int m = 0; m < NMOM; ++m) {
+    cx[m] = Y[(long)x * NO + 5 * n + 1 + m];
+    inv_s[m] = 1.0 / scale[m];
+  }
   const double rx = Y[(long)x * NO + 5 * n];
-  const double inv_s = 1.0 / scale[n];
-  const long base = ((long)n * N + x) * N;
-  double l = 0.0, g[RANK] = {0.0, 0.0, 0.0, 0.0};
-  __shared__ double red[5][256];
+  double l = 0.0, g[NMOM] = {0.0, 0.0, 0.0, 0.0};
+  __shared__ double red[1 + NMOM][256];
   __shared__ double dpxx;
   for (int y = tid; y < N; y += 256) {
-    double p = (x == y) ? rx : 0.0;
-    double wy[RANK];
+    const long xy = (long)x * N + y;
+    double p = (x == y) ? rx : 0.0, ut[NMOM];
 #pragma unroll
-    for (int k = 0; k < RANK; ++k) {
-      wy[k] = Y[(long)y * NO + 5 * n + 1 + k];
-      p += sg[k] * wx[k] * wy[k];
+    for (int m = 0; m < NMOM; ++m) {
+      ut[m] = m0[m * nn + xy] * inv_s[m];
+      p += (cx[m] + (double)Y[(long)y * NO + 5 * n + 1 + m]) * ut[m];
     }
-    const double t = (mc[base + y] - m0[base + y]) * inv_s;
+    const double t = (mc[n * nn + xy] - m0[n * nn + xy]) * inv_s[n];
     const double r = p - t;
     l += r * r;
     const double dp = 2.0 * r / N;
     if (x == y) dpxx = dp;
 #pragma unroll
-    for (int k = 0; k < RANK; ++k) g[k] += dp * wy[k];
+    for (int m = 0; m < NMOM; ++m) g[m] += dp * ut[m];
   }
   red[0][tid] = l;
 #pragma unroll
-  for (int k = 0; k < RANK; ++k) red[1 + k][tid] = g[k];
+  for (int m = 0; m < NMOM; ++m) red[1 + m][tid] = g[m];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (tid < w)
 #pragma unroll
-      for (int q = 0; q < 5; ++q) red[q][tid] += red[q][tid + w];
+      for (int q = 0; q < 1 + NMOM; ++q) red[q][tid] += red[q][tid + w];
     __syncthreads();
   }
   if (tid == 0) {
     lpart[(long)n * N + x] = red[0][0] / N;
     dY[(long)x * NO + 5 * n] = (float)dpxx;
 #pragma unroll
-    for (int k = 0; k < RANK; ++k) dY[(long)x * NO + 5 * n + 1 + k] = (float)(2.0 * sg[k] * red[1 + k][0]);
+    for (int m = 0; m < NMOM; ++m) dY[(long)x * NO + 5 * n + 1 + m] = (float)(2.0 * red[1 + m][0]);
   }
 }
 
@@ -275,8 +276,9 @@ __global__ __launch_bounds__(256) void features_kernel(int N, int nocc, const do
   }
 }
 
-// dm[n][x][y] = s_n (delta_xy r_n(x) + sum_k S_k W_n(x,k) W_n(y,k))
+// dm[n][x][y] = s_n (delta_xy r_n(x) + sum_m (c_nm(x) + c_nm(y)) m0[m][x][y] / s_m)
 __global__ void correction_kernel(int N, const float* __restrict__ Y,
+                                  const double* __restrict__ m0,
                                   const double* __restrict__ scale, double* __restrict__ dm) {
   const long nn = (long)N * N, total = NMOM * nn;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
@@ -287,8 +289,9 @@ __global__ void correction_kernel(int N, const float* __restrict__ Y,
     const float* yx = Y + (long)x * NO + 5 * n;
     const float* yy = Y + (long)y * NO + 5 * n;
     double p = (x == y) ? (double)yx[0] : 0.0;
-    p += (double)yx[1] * yy[1] + (double)yx[2] * yy[2] - (double)yx[3] * yy[3] -
-         (double)yx[4] * yy[4];
+#pragma unroll
+    for (int m = 0; m < NMOM; ++m)
+      p += ((double)yx[1 + m] + (double)yy[1 + m]) * m0[m * nn + r] / scale[m];
     dm[i] = scale[n] * p;
   }
 }
@@ -609,7 +612,7 @@ agf2_status agf2_mlp_predict_correction(agf2_handle_t hh, agf2_mlp_t p, int nphy
     AGF2_CHECK_LAUNCH();
     forward(net, nphys, X, Y, h.stream);
     hipLaunchKernelGGL(correction_kernel, dim3(grid1(4L * nphys * nphys)), dim3(256), 0,
-                       h.stream, nphys, Y, s, dm);
+                       h.stream, nphys, Y, m0, s, dm);
     AGF2_CHECK_LAUNCH();
   });
 }

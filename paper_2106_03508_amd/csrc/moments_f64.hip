@@ -274,7 +274,9 @@ __device__ void syrk_tile(const SyrkF64& a, int t, int s, double (*X)[BK][LD],
 
 __global__ __launch_bounds__(NT) void syrk_f64_kernel(SyrkF64 a) {
   __shared__ double X[2][BK][LD], Y[2][BK][LD], W[2][BK];
-  syrk_tile(a, blockIdx.x, blockIdx.y, X, Y, W);
+  // split-major items dealt to XCDs in contiguous ranges (one K range per L2)
+  const long item = xcd_remap(blockIdx.x, (long)a.tiles * a.nsplit);
+  syrk_tile(a, (int)(item % a.tiles), (int)(item / a.tiles), X, Y, W);
 }
 
 __global__ __launch_bounds__(NT) void syrk_f64_grouped(const SyrkF64* jobs, const long* prefix,
@@ -329,7 +331,8 @@ void launch_slab_f64(int tc, const SlabF64& a, hipStream_t st) {
 }
 
 void launch_syrk_f64(const SyrkF64& a, hipStream_t st) {
-  hipLaunchKernelGGL(syrk_f64_kernel, dim3(a.tiles, a.nsplit), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL(syrk_f64_kernel, dim3((unsigned)((long)a.tiles * a.nsplit)), dim3(NT), 0,
+                     st, a);
   AGF2_CHECK_LAUNCH();
 }
 

@@ -15,8 +15,8 @@
 //     16-bit pairs; the SYRK kernel takes all four products of Z (the lo*lo
 //     term of a square is never negative, so dropping it would bias U0),
 //     accumulates in float32 over chunks of KC columns and folds each chunk
-//     into float64 accumulators with Kahan compensation; per-split float64
-//     partials are summed in a fixed order.
+//     into float64 accumulators; per-split float64 partials are summed in a
+//     fixed order.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -165,8 +165,9 @@ constexpr int GT = 256;
 
 template <bool F16>
 __global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmArgs a) {
-  __shared__ u16x8 sA[2][GT][KVP];   // hi, lo
-  __shared__ u16x8 sB[2][GT][KVP];
+  // two stages (double buffer) x (hi, lo): 160 KiB, the whole LDS of a CU
+  __shared__ u16x8 sA[2][2][GT][KVP];
+  __shared__ u16x8 sB[2][2][GT][KVP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long G = (long)a.tiles_m * a.tiles_n;
   const long logical = xcd_remap(blockIdx.x, G);
@@ -193,14 +194,14 @@ __global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmArgs a) {
       pb[4 + i] = ob[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Bl + ob[i] + kb) : zero8;
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = (tid >> 2) + 64 * i;
-      sA[0][r][kv] = pa[i];
-      sA[1][r][kv] = pa[4 + i];
-      sB[0][r][kv] = pb[i];
-      sB[1][r][kv] = pb[4 + i];
+      sA[buf][0][r][kv] = pa[i];
+      sA[buf][1][r][kv] = pa[4 + i];
+      sB[buf][0][r][kv] = pb[i];
+      sB[buf][1][r][kv] = pb[4 + i];
     }
   };
   const int fr = lane & 15, fk = lane >> 4;
@@ -211,21 +212,24 @@ __global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmArgs a) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int nsteps = a.Qs / KS;
+  // stage k lives in buffer k & 1: the next stage's global loads are issued
+  // before this stage's MFMAs and written to the other buffer after them, so
+  // one barrier per stage separates every write from the reads of that buffer
   load(0);
+  store(0);
+  __syncthreads();
   for (int step = 0; step < nsteps; ++step) {
-    __syncthreads();
-    store();
-    __syncthreads();
+    const int buf = step & 1;
     if (step + 1 < nsteps) load((step + 1) * KS);
     u16x8 ah[8], al[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      ah[i] = sA[0][wm + 16 * i + fr][fk];
-      al[i] = sA[1][wm + 16 * i + fr][fk];
+      ah[i] = sA[buf][0][wm + 16 * i + fr][fk];
+      al[i] = sA[buf][1][wm + 16 * i + fr][fk];
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const u16x8 bh = sB[0][wn + 16 * j + fr][fk], bl = sB[1][wn + 16 * j + fr][fk];
+      const u16x8 bh = sB[buf][0][wn + 16 * j + fr][fk], bl = sB[buf][1][wn + 16 * j + fr][fk];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         acc[i][j] = mfma<F16>(ah[i], bh, acc[i][j]);
@@ -233,6 +237,8 @@ __global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmArgs a) {
         acc[i][j] = mfma<F16>(al[i], bh, acc[i][j]);
       }
     }
+    if (step + 1 < nsteps) store(buf ^ 1);
+    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 8; ++i)
@@ -262,23 +268,21 @@ struct PairArgs {
   u16* Zh; u16* Zl; u16* Wh; u16* Wl; long ldz;
 };
 
+// Grid: (element blocks of N * nc, pairs); one workgroup row per pole pair.
 template <bool F16>
-__global__ void pair_split_kernel(PairArgs a) {
-  const long tot = (long)a.npairs * a.N * a.nc;
+__global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
   // sqrt(1/2) and sqrt(3/2) as float pairs: every column is multiplied with
   // one rounding (fma), so the constants' own float rounding does not bias
   // all P or all M columns alike
   const float cp_hi = 0.707106769084930419921875f, cp_lo = 1.2101617485882343e-08f;
   const float cm_hi = 1.22474491596221923828125f, cm_lo = -4.4570629853524224e-08f;
-  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(idx % a.nc);
-    const long t = idx / a.nc;
-    const int x = (int)(t % a.N);
-    const int pr = (int)(t / a.N);
-    const int p = a.pa[pr], q = a.pb[pr];
-    const long col = a.pcol[pr] - a.col_base + c;
-    const long o = (long)x * a.ldz + col;
+  const int pr = blockIdx.y;
+  const int p = a.pa[pr], q = a.pb[pr];
+  const long colbase = a.pcol[pr] - a.col_base;
+  const int per = a.N * a.nc;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < per; e += gridDim.x * 256) {
+    const int x = e / a.nc, c = e - x * a.nc;
+    const long o = (long)x * a.ldz + colbase + c;
     float x1 = a.X1[((long)(p - a.P0) * a.N + x) * a.ld1 + (long)(q - a.P1) * a.nc + c];
     if constexpr (F16)
       x1 = ldexpf(x1, a.eR[p] + a.eS[(long)q * a.sEp + (long)c * a.sEc] - 2 * EMAX);
@@ -310,28 +314,25 @@ struct SyrkArgs {
   int N; long K; long kper;
   double u0scale, u1scale;   // 2^-2fZ, 2^-(fZ+fW)
   double* part; long part_stride;
+  int tiles, nsplit;         // lower-triangle tiles, K splits (grid = tiles * nsplit)
 };
 
 constexpr int TS = 64;   // SYRK output tile
 
-__device__ __forceinline__ void kahan_add(double& s, double& c, double v) {
-  const double y = v - c;
-  const double t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
-
 template <bool F16>
-__global__ __launch_bounds__(NT) void syrk_split_kernel(SyrkArgs a) {
+__global__ __launch_bounds__(NT, 2) void syrk_split_kernel(SyrkArgs a) {
   __shared__ u16x8 sX[4][TS][KVP];   // Z hi, Z lo, wZ hi, wZ lo (x rows)
   __shared__ u16x8 sY[2][TS][KVP];   // Z hi, Z lo (y rows)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int t = blockIdx.x;
+  // (split, tile) work items numbered split-major and dealt to XCDs in
+  // contiguous ranges, so the tiles reading one K range share an L2
+  const long item = xcd_remap(blockIdx.x, (long)a.tiles * a.nsplit);
+  const int t = (int)(item % a.tiles);
   int xt = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((xt + 1) * (xt + 2) / 2 <= t) ++xt;
   while (xt * (xt + 1) / 2 > t) --xt;
   const int yt = t - xt * (xt + 1) / 2;
-  const int s = blockIdx.y;
+  const int s = (int)(item / a.tiles);
   const long k0 = (long)s * a.kper, k1 = std::min(a.K, k0 + a.kper);
   if (k1 <= k0) return;
   const int x0 = xt * TS, y0 = yt * TS;
@@ -382,9 +383,11 @@ __global__ __launch_bounds__(NT) void syrk_split_kernel(SyrkArgs a) {
   const int fr = lane & 15, fk = lane >> 4;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   // hi*hi products and the ~2^-11 smaller cross products (hi*lo, lo*hi,
-  // lo*lo) accumulate separately, so the large sum is rounded once per step
+  // lo*lo) accumulate separately, so the large sum is rounded once per step;
+  // every KC_STEPS steps both are folded into float64 sums (a few thousand
+  // float64 additions per output element in all, far below the float32 error)
   f4 u0[2][2], u1[2][2], v0[2][2], v1[2][2];
-  double s0[2][2][4], e0[2][2][4], s1[2][2][4], e1[2][2][4];
+  double s0[2][2][4], s1[2][2][4];
   const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -392,7 +395,7 @@ __global__ __launch_bounds__(NT) void syrk_split_kernel(SyrkArgs a) {
     for (int j = 0; j < 2; ++j) {
       u0[i][j] = u1[i][j] = v0[i][j] = v1[i][j] = z4;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) s0[i][j][r] = e0[i][j][r] = s1[i][j][r] = e1[i][j][r] = 0.0;
+      for (int r = 0; r < 4; ++r) s0[i][j][r] = s1[i][j][r] = 0.0;
     }
   auto flush = [&]() {
 #pragma unroll
@@ -401,10 +404,8 @@ __global__ __launch_bounds__(NT) void syrk_split_kernel(SyrkArgs a) {
       for (int j = 0; j < 2; ++j) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          kahan_add(s0[i][j][r], e0[i][j][r],
-                    a.u0scale * ((double)u0[i][j][r] + (double)v0[i][j][r]));
-          kahan_add(s1[i][j][r], e1[i][j][r],
-                    a.u1scale * ((double)u1[i][j][r] + (double)v1[i][j][r]));
+          s0[i][j][r] += a.u0scale * ((double)u0[i][j][r] + (double)v0[i][j][r]);
+          s1[i][j][r] += a.u1scale * ((double)u1[i][j][r] + (double)v1[i][j][r]);
         }
         u0[i][j] = u1[i][j] = v0[i][j] = v1[i][j] = z4;
       }
@@ -456,8 +457,8 @@ __global__ __launch_bounds__(NT) void syrk_split_kernel(SyrkArgs a) {
         const int y = y0 + wn + 16 * j + fr;
         if (x >= a.N || y >= a.N) continue;
         const long o = (long)x * a.N + y;
-        P0[o] += s0[i][j][r] - e0[i][j][r];
-        P1[o] += s1[i][j][r] - e1[i][j][r];
+        P0[o] += s0[i][j][r];
+        P1[o] += s1[i][j][r];
       }
 }
 
@@ -532,7 +533,7 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
   // X1 = R[block ib] S[block jb]^T and X2 = R[block jb] S[block ib]^T are
   // float32 buffers of kb N x kb nc each (<= ~256 MiB)
   int kb = (int)std::floor(std::sqrt((double)(1L << 26) / ((double)N * nc)));
-  kb = std::max(1, std::min(kb, np));
+  kb = std::max(1, std::min({kb, np, 255}));   // <= 255^2 pairs per chunk (grid y limit)
   const int nblk = (np + kb - 1) / kb;
   // pair list ordered by block pair, with chunk-local column offsets
   std::vector<int> hpa, hpb;
@@ -613,9 +614,12 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
       {
         const long tot = (long)pa.npairs * N * nc;
         ProfScope ps(h, "moments.pair", 0.0, 4.0 * 2.0 * tot + 8.0 * N * (double)Kc);
+        const long per = (long)N * nc;
+        AGF2_REQUIRE(per < (1L << 31) - 256 && pa.npairs <= 65535, "pair chunk too large");
         hipLaunchKernelGGL((pair_split_kernel<F16>),
-                           dim3((unsigned)std::min<long>((tot + 255) / 256, 65536)), dim3(256), 0,
-                           st, pa);
+                           dim3((unsigned)std::min<long>((per + 255) / 256, 16384),
+                                (unsigned)pa.npairs),
+                           dim3(256), 0, st, pa);
         AGF2_CHECK_LAUNCH();
       }
       int nsplit = (int)std::min<long>(nsplit_max, std::max<long>(1, Kc / 1024));
@@ -629,7 +633,9 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
       ya.part = part; ya.part_stride = part_stride;
       {
         ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 0.0) * Kc);
-        hipLaunchKernelGGL((syrk_split_kernel<F16>), dim3(nlower, nsplit), dim3(NT), 0, st, ya);
+        ya.tiles = nlower; ya.nsplit = nsplit;
+        hipLaunchKernelGGL((syrk_split_kernel<F16>), dim3((unsigned)(nlower * nsplit)), dim3(NT),
+                           0, st, ya);
         AGF2_CHECK_LAUNCH();
       }
     }
