@@ -328,10 +328,12 @@ agf2_status agf2_profile_get(agf2_handle_t handle, int idx, const char** name,
  *   +1 occupied / -1 virtual, U_n[x][x] / s_n (4), log s_n (4),
  * with s_n the mean |diagonal| of U_n (at least 1e-30).
  * Outputs (float32 [N][20]): for moment n, y[5n] = r_n(x) and
- * y[5n+1..5n+4] = W_n(x, 0..3); the correction is
- *   Delta U_n = s_n (diag(r_n) + W_n diag(1, 1, -1, -1) W_n^T).
- * Loss of one system, T_n = (U_n(converged) - U_n(iteration 0)) / s_n:
- *   sum_n || diag(r_n) + W_n S W_n^T - T_n ||_F^2 / N.
+ * y[5n+1+m] = c_nm(x), m = 0..3; the correction is a diagonal term plus a
+ * symmetric per-orbital rescaling of the four iteration-0 moments,
+ *   Delta U_n[x][y] = s_n (delta_xy r_n(x)
+ *                          + sum_m (c_nm(x) + c_nm(y)) U_m[x][y] / s_m).
+ * Loss of one system, T_n = (U_n(converged) - U_n(iteration 0)) / s_n and
+ * P_n = Delta U_n / s_n:  sum_n || P_n - T_n ||_F^2 / N.
  *
  * Parameters: float32, flat, in the order W1 [12][256], b1 [256],
  * W2 [256][256], b2 [256], W3 [256][20], b3 [20] (weights [in][out]).

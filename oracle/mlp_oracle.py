@@ -7,12 +7,16 @@ What it computes. The warm start corrects the iteration-0 self-energy
 moments U_n (n = 0<, 1<, 0>, 1>; zeroth and first moments of the lesser and
 greater parts) towards the converged ones before the first compression. A
 small network sees each physical orbital x on its own and emits, for every
-moment n, a diagonal entry r_n(x) and a row W_n(x, :) of a rank-4 factor, so
+moment n, a diagonal entry r_n(x) and four scaling coefficients c_nm(x), one
+per iteration-0 moment m, so that
 
-    Delta U_n = s_n * (diag(r_n) + W_n S W_n^T),   S = diag(1, 1, -1, -1),
+    Delta U_n = s_n * P_n,
+    P_n[x, y] = delta_xy r_n(x) + sum_m (c_nm(x) + c_nm(y)) U_m[x, y] / s_m,
 
-where s_n is the mean absolute diagonal of the iteration-0 moment (a scale
-that makes the network's outputs dimensionless). Per-orbital features:
+i.e. a diagonal correction plus a symmetric per-orbital rescaling of the
+four iteration-0 moments; s_n is the mean absolute diagonal of U_n (a scale
+that makes outputs and targets dimensionless). Output column 5n holds r_n,
+columns 5n+1 .. 5n+4 hold c_n0 .. c_n3. Per-orbital features:
     0  e_x                        orbital energy
     1  e_x - mu0                  mu0 = (e_HOMO + e_LUMO) / 2
     2  e_LUMO - e_HOMO            the gap (same for every orbital)
@@ -29,7 +33,6 @@ float64, mirroring a network with FP16 weights and FP32 accumulation.
 
 Loss of one system (targets from a converged run):
     T_n = (U_n(converged) - U_n(iteration 0)) / s_n,
-    P_n = diag(r_n) + W_n S W_n^T,
     loss = sum_n ||P_n - T_n||_F^2 / N.
 Adam (Kingma and Ba) with bias-corrected first and second moments.
 """
@@ -38,8 +41,7 @@ from __future__ import annotations
 import numpy as np
 from scipy.special import erf
 
-NF, NH, NO, RANK, NMOM = 12, 256, 20, 4, 4
-S_SIGN = np.array([1.0, 1.0, -1.0, -1.0])
+NF, NH, NO, NMOM = 12, 256, 20, 4
 LAYOUT = [("W1", (NF, NH)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)),
           ("W3", (NH, NO)), ("b3", (NO,))]
 NPARAM = sum(int(np.prod(s)) for _, s in LAYOUT)
@@ -104,30 +106,34 @@ def forward(theta, X, fp16=True):
     return Y, dict(X0=X0, Z1=Z1, A1=A1, Z2=Z2, A2=A2, W1=W1, W2=W2, W3=W3)
 
 
-def head(Y):
-    """Normalised corrections P [4, N, N] from the outputs Y [N, 20]."""
+def head(Y, m0, s):
+    """Normalised corrections P [4, N, N] from the outputs Y [N, 20], the
+    iteration-0 moments m0 [4, N, N] and their scales s [4]."""
     N = Y.shape[0]
+    Ut = np.asarray(m0) / s[:, None, None]
     P = np.empty((NMOM, N, N))
     for n in range(NMOM):
-        r = Y[:, 5 * n]
-        W = Y[:, 5 * n + 1:5 * n + 1 + RANK]
-        P[n] = np.diag(r) + (W * S_SIGN) @ W.T
+        P[n] = np.diag(Y[:, 5 * n])
+        for m in range(NMOM):
+            c = Y[:, 5 * n + 1 + m]
+            P[n] += (c[:, None] + c[None, :]) * Ut[m]
     return P
 
 
 def loss_grad(Y, m0, mconv, s):
     """Loss of one system and its gradient with respect to Y."""
     N = Y.shape[0]
-    P = head(Y)
+    P = head(Y, m0, s)
     T = (np.asarray(mconv) - np.asarray(m0)) / s[:, None, None]
+    Ut = np.asarray(m0) / s[:, None, None]
     R = P - T
     loss = float(np.sum(R * R)) / N
     dY = np.zeros_like(Y)
     for n in range(NMOM):
         dP = 2.0 * R[n] / N                       # symmetric
-        W = Y[:, 5 * n + 1:5 * n + 1 + RANK]
         dY[:, 5 * n] = np.diag(dP)
-        dY[:, 5 * n + 1:5 * n + 1 + RANK] = 2.0 * (dP @ W) * S_SIGN
+        for m in range(NMOM):
+            dY[:, 5 * n + 1 + m] = 2.0 * np.sum(dP * Ut[m], axis=1)
     return loss, dY
 
 
@@ -160,4 +166,4 @@ def predict_correction(theta, e_mf, nocc, m0, fp16=True):
     """Delta U [4, N, N] to add to the iteration-0 moments."""
     X, s = features(e_mf, nocc, m0)
     Y, _ = forward(theta, X, fp16)
-    return head(Y) * s[:, None, None]
+    return head(Y, m0, s) * s[:, None, None]

@@ -276,7 +276,9 @@ __global__ __launch_bounds__(256) void features_kernel(int N, int nocc, const do
   }
 }
 
-// dm[n][x][y] = s_n (delta_xy r_n(x) + sum_m (c_nm(x) + c_nm(y)) m0[m][x][y] / s_m)
+// dm[n][x][y] = s_n (delta_xy r_n(x) + sum_m (c_nm(x) + c_nm(y)) m0[m][x][y] / s_m), with
+// m0[m][x][y] taken as the mean of the (x, y) and (y, x) entries so that dm is
+// exactly symmetric
 __global__ void correction_kernel(int N, const float* __restrict__ Y,
                                   const double* __restrict__ m0,
                                   const double* __restrict__ scale, double* __restrict__ dm) {
@@ -290,8 +292,10 @@ __global__ void correction_kernel(int N, const float* __restrict__ Y,
     const float* yy = Y + (long)y * NO + 5 * n;
     double p = (x == y) ? (double)yx[0] : 0.0;
 #pragma unroll
-    for (int m = 0; m < NMOM; ++m)
-      p += ((double)yx[1 + m] + (double)yy[1 + m]) * m0[m * nn + r] / scale[m];
+    for (int m = 0; m < NMOM; ++m) {
+      const double u = 0.5 * (m0[m * nn + r] + m0[m * nn + (long)y * N + x]);
+      p += ((double)yx[1 + m] + (double)yy[1 + m]) * u / scale[m];
+    }
     dm[i] = scale[n] * p;
   }
 }

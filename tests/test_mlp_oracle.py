@@ -61,7 +61,7 @@ def test_loss_grad_matches_finite_differences():
     s = np.array([0.5, 2.0, 1.0, 3.0])
     loss, dY = M.loss_grad(Y, m0, mconv, s)
     T = (mconv - m0) / s[:, None, None]
-    assert abs(loss - np.sum((M.head(Y) - T) ** 2) / N) < 1e-12
+    assert abs(loss - np.sum((M.head(Y, m0, s) - T) ** 2) / N) < 1e-12
     h = 1e-6
     for i in range(N):
         for j in range(M.NO):
@@ -88,19 +88,28 @@ def test_adam_closed_form():
     assert np.array_equal(t3, theta)
 
 
-def test_head_rank4_structure():
+def test_head_structure():
     N = 5
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal((4, N, N))
+    m0 = a + a.transpose(0, 2, 1)
+    s = np.array([1.0, 2.0, 4.0, 0.5])
     Y = np.zeros((N, M.NO))
     r = np.arange(1.0, N + 1)
     Y[:, 0] = r
-    P = M.head(Y)
+    P = M.head(Y, m0, s)
     assert np.array_equal(P[0], np.diag(r)) and not P[1:].any()
     w = np.array([1.0, -2.0, 0.5, 0.0, 3.0])
-    for k, sgn in enumerate([1.0, 1.0, -1.0, -1.0]):
+    for m in range(4):
         Y = np.zeros((N, M.NO))
-        Y[:, 5 * 2 + 1 + k] = w           # moment 2, rank column k
-        P = M.head(Y)
-        assert np.array_equal(P[2], sgn * np.outer(w, w))
+        Y[:, 5 * 2 + 1 + m] = w           # moment 2, scaling of iteration-0 moment m
+        P = M.head(Y, m0, s)
+        assert np.allclose(P[2], (w[:, None] + w[None, :]) * m0[m] / s[m], rtol=0, atol=1e-15)
+        assert not P[[0, 1, 3]].any()
+    # a constant coefficient c on moment n itself rescales it by (1 + 2c)
+    Y = np.zeros((N, M.NO))
+    Y[:, 5 * 1 + 1 + 1] = 0.25
+    assert np.allclose(s[1] * M.head(Y, m0, s)[1], 0.5 * m0[1], rtol=0, atol=1e-14)
 
 
 def test_features_hand_case():
