@@ -197,6 +197,26 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings),
+    or None when there is none or the kernel's source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    rec = t.get(kernel)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec
+
+
 def log(msg):
     print(f"# {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
@@ -321,8 +341,14 @@ def main():
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None, "avg_launch_ms": round(avg_ms, 4),
                      "flops_per_launch": d["flops"] / d["launches"]},
+        "traffic_note": None,
         "cpu_baseline": None,
     }
+    tr = measured_traffic(dom)
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["bytes_per_launch"]
+        out["traffic_note"] = (f"HBM bytes per launch of {dom} (FETCH_SIZE + WRITE_SIZE, scaled "
+                               f"by a 1 GiB copy's readings; {tr['profile']})")
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample")
         t_full, info = cpu_baseline(L, eps, nocc, args.cpu_occ_sample, args.cpu_vir_sample,

@@ -333,6 +333,7 @@ struct FockLoop {
   double* hlam; double* hw;
   double solved_shift = NAN;
   const double* solved_F = nullptr;
+  double last_change = 0.0;   // |shift change| of the previous fit
   int n_eig = 0;
 
   FockLoop(Handle& hh, int N_, int Q_, int naux_, const double* L_, const double* e_,
@@ -394,7 +395,12 @@ struct FockLoop {
         return count_n(nocc) - nelec;
       };
       const double dir = g0 < 0 ? 1.0 : -1.0;
-      double a_ = shift, ga = g0, b = a_, gb = ga, step = o.step0;
+      // first bracket step: four times the previous fit's change of the shift
+      // (the change shrinks from one density cycle to the next), never more
+      // than step0; a miss costs a doubling
+      double step = o.step0;
+      if (last_change > 0.0) step = std::min(o.step0, std::max(4.0 * last_change, 1e-7));
+      double a_ = shift, ga = g0, b = a_, gb = ga;
       while (true) {
         b = shift + dir * std::min(step, o.bracket);
         gb = g(b);
@@ -421,8 +427,11 @@ struct FockLoop {
           }
         }
       }
+      last_change = std::fabs(x - shift);
       shift = x;
-      Aufbau an = solve(F, shift);
+      // the last count was evaluated at x: reuse that eigendecomposition
+      Aufbau an = (solved_shift == shift && solved_F == F) ? aufbau(n, hlam, hw, nelec)
+                                                           : solve(F, shift);
       cnt = an.count;
       if (an.n == nocc) return shift;
       nocc = an.n;

@@ -69,9 +69,12 @@ struct Gemm {
   double* C = nullptr;
   long sCb = 0, sCs = 0, sCm = 0, sCn = 0;
   double alpha = 1.0, beta = 0.0;
+  bool lower = false;   // square outputs: only tiles on or below the diagonal are written
 };
 void gemm_f64(const Gemm& g, hipStream_t stream);
 void gemm_f64_padded(const Gemm& g, int Npad, hipStream_t stream);
+int gemm_f64_slots();               // resident GEMM workgroups on the device
+int gemm_f64_tiles(int M, int N);   // output tiles of an M x N product
 
 // Sum `nslice` [rows][cols] slices spaced `slice_stride` apart into out
 // (fixed order), optionally scaling: out = scale * sum_s in[s] (+ out if add).

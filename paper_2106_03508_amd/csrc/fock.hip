@@ -39,7 +39,10 @@ __global__ void fock_combine_kernel(const double* L, const double* rho, int Q, i
        i += (long)gridDim.x * blockDim.x) {
     double j = 0.0;
     for (int q = 0; q < Q; ++q) j += rho[q] * L[q * nn + i];
-    F[i] = h[i] + alpha * (j - 0.5 * K[i]);
+    // K is symmetric and only its lower triangle is built
+    const int p = (int)(i / N), r = (int)(i % N);
+    const long kl = p >= r ? i : (long)r * N + p;
+    F[i] = h[i] + alpha * (j - 0.5 * K[kl]);
   }
 }
 
@@ -123,15 +126,25 @@ void fock_build(Handle& h, int N, int Q, const double* L, const double* hcore,
                 const double* D, double alpha, double* F) {
   hipStream_t st = h.stream;
   const long nn = (long)N * N;
-  ProfScope ps(h, "fock.jk", 4.0 * Q * (double)nn * N + 4.0 * Q * (double)nn,
+  ProfScope ps(h, "fock.jk", 3.0 * Q * (double)nn * N + 4.0 * Q * (double)nn,
                8.0 * (3.0 * Q * nn + 3.0 * nn));
   double* rho = h.ws_fock[0].as<double>(Q);
   hipLaunchKernelGGL(rho_kernel, dim3(Q), dim3(RT), 0, st, L, D, N, rho);
   AGF2_CHECK_LAUNCH();
   // exchange K[p][q] = sum_Q (L_Q D L_Q)[p][q], Q processed in chunks:
   //   V[Q][p][r] = sum_s L[Q][p][s] D[s][r]; K += sum_{Q,r} V[Q][p][r] L[Q][r][q]
-  const int tiles = ((N + 63) / 64) * ((N + 63) / 64);
-  const int nsplit = std::max(1, std::min(32, 1024 / std::max(1, tiles)));
+  // (the second product on the lower triangle only: K is symmetric)
+  // split count of the lower-triangle product: the one whose whole rounds of
+  // resident workgroups give the least work per split (ties: fewer splits)
+  const int tside = (int)std::lround(std::sqrt((double)gemm_f64_tiles(N, N)));
+  const long tlow = (long)tside * (tside + 1) / 2;
+  const int slots = gemm_f64_slots();
+  int nsplit = 1;
+  double best = 1e300;
+  for (int ns = 1; ns <= 32; ++ns) {
+    const double t = (double)((tlow * ns + slots - 1) / slots) / ns;
+    if (t < best - 1e-12) { best = t; nsplit = ns; }
+  }
   const long chunk_bytes = 1L << 30;
   const int QC = (int)std::max<long>(1, std::min<long>(Q, chunk_bytes / (8 * nn)));
   double* V = h.ws_fock[1].as<double>((long)QC * nn);
@@ -152,6 +165,7 @@ void fock_build(Handle& h, int N, int Q, const double* L, const double* hcore,
     g2.B = L + (long)q0 * nn; g2.sBr = nn; g2.sBk = N; g2.sBn = 1;
     g2.C = Kp; g2.sCs = nn; g2.sCm = N; g2.sCn = 1;
     g2.beta = 1.0;
+    g2.lower = true;
     gemm_f64(g2, st);
   }
   sum_slices(Kp, nn, nsplit, nn, K, 1.0, false, st);

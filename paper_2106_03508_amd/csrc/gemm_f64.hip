@@ -21,6 +21,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g, int Npad) {
   const int lane = tid & 63, wave = tid >> 6;
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  if (g.lower && tn > tm) return;   // uniform over the workgroup
   const int b = blockIdx.y, s = blockIdx.z;
   const int m0 = tm * BM, n0 = tn * BN;
   const int r_per = (g.R + g.nsplit - 1) / g.nsplit;
@@ -127,6 +128,19 @@ __global__ void sum_slices_kernel(const double* in, long stride, int nslice,
 }
 
 }  // namespace
+
+int gemm_f64_slots() {
+  static int cached = 0;
+  if (cached > 0) return cached;
+  int dev = 0, cus = 0, per = 0;
+  AGF2_HIP(hipGetDevice(&dev));
+  AGF2_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  AGF2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gemm_f64_kernel<true, true>, NT, 0));
+  cached = std::max(1, cus) * std::max(1, per);
+  return cached;
+}
+
+int gemm_f64_tiles(int M, int N) { return ((M + BM - 1) / BM) * ((N + BN - 1) / BN); }
 
 void gemm_f64_padded(const Gemm& g, int Npad, hipStream_t stream) {
   if (g.M <= 0 || g.N <= 0) return;

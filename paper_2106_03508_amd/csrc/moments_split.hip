@@ -517,6 +517,36 @@ struct PartScales {
 
 }  // namespace
 
+// Workgroups resident on the whole device for a kernel (compute units x
+// resident workgroups per unit), queried once per kernel.
+template <class K>
+int device_slots(K kernel, int& cache) {
+  if (cache > 0) return cache;
+  int dev = 0, cus = 0, per = 0;
+  AGF2_HIP(hipGetDevice(&dev));
+  AGF2_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  AGF2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, NT, 0));
+  cache = std::max(1, cus) * std::max(1, per);
+  return cache;
+}
+
+// K splits of one SYRK launch: up to nmax (and about Kc / 512), chosen so that
+// tiles x splits fills whole rounds of the device's resident workgroups.
+int choose_splits(long Kc, int tiles, int nmax, int slots) {
+  const int hi = (int)std::max<long>(1, std::min<long>(nmax, Kc / 512));
+  int best = hi;
+  double best_eff = -1.0;
+  for (int ns = hi; ns >= std::max(1, hi / 2); --ns) {
+    const long items = (long)tiles * ns;
+    const double eff = (double)items / (double)(((items + slots - 1) / slots) * slots);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = ns;
+    }
+  }
+  return best;
+}
+
 template <bool F16>
 static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, const u16* Rl,
                                long sRp, long sRx, const u16* Sh, const u16* Sl, long sSp,
@@ -532,6 +562,7 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
   // blocks of kb poles; a chunk is one block pair (ib <= jb), whose slabs
   // X1 = R[block ib] S[block jb]^T and X2 = R[block jb] S[block ib]^T are
   // float32 buffers of kb N x kb nc each (<= ~256 MiB)
+  static int syrk_slots = 0;
   int kb = (int)std::floor(std::sqrt((double)(1L << 26) / ((double)N * nc)));
   kb = std::max(1, std::min({kb, np, 255}));   // <= 255^2 pairs per chunk (grid y limit)
   const int nblk = (np + kb - 1) / kb;
@@ -622,7 +653,8 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
                            dim3(256), 0, st, pa);
         AGF2_CHECK_LAUNCH();
       }
-      int nsplit = (int)std::min<long>(nsplit_max, std::max<long>(1, Kc / 1024));
+      int nsplit = choose_splits(Kc, nlower, nsplit_max,
+                                 device_slots(syrk_split_kernel<F16>, syrk_slots));
       long kper = (Kc + nsplit - 1) / nsplit;
       kper = (kper + KS - 1) / KS * KS;
       nsplit = (int)((Kc + kper - 1) / kper);
