@@ -232,6 +232,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-occ-sample", type=int, default=1)
     ap.add_argument("--cpu-vir-sample", type=int, default=1)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one plain 1 GiB device copy (a calibration dispatch of "
+                         "known size for HBM counters; outside the timed region)")
     ap.add_argument("--batch-poles", default="dressed3n", choices=["hf", "dressed3n"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="batch64: wall time budget of the oracle sample")
@@ -244,6 +247,13 @@ def main():
     import torch
     from paper_2106_03508_amd import agf2
 
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 1 GiB read, 1 GiB written")
     if args.workload == "batch64":
         return main_batch(args)
     wl = WORKLOADS[args.workload]
