@@ -324,9 +324,11 @@ agf2_status agf2_profile_get(agf2_handle_t handle, int idx, const char** name,
  *
  * Features of physical orbital x (float32 [N][12]), from the mean-field
  * energies e and the iteration-0 moments U_n (n = 0<, 1<, 0>, 1>):
- *   e_x, e_x - mu0 (mu0 = (e_HOMO + e_LUMO)/2), e_LUMO - e_HOMO,
- *   +1 occupied / -1 virtual, U_n[x][x] / s_n (4), log s_n (4),
- * with s_n the mean |diagonal| of U_n (at least 1e-30).
+ *   e_x, e_x - mu0 (mu0 = (e_HOMO + e_LUMO)/2), gap = e_LUMO - e_HOMO,
+ *   +1 occupied / -1 virtual, U_n[x][x] / s_n (4), log(s_1/s_0),
+ *   log(s_2/s_0), log(s_3/s_2), (e_x - mu0) / gap,
+ * with s_n the mean |diagonal| of U_n (at least 1e-30); no absolute moment
+ * scale enters, so the features do not drift with the system size.
  * Outputs (float32 [N][20]): for moment n, y[5n] = r_n(x) and
  * y[5n+1+m] = c_nm(x), m = 0..3; the correction is a diagonal term plus a
  * symmetric per-orbital rescaling of the four iteration-0 moments,

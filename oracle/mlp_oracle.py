@@ -22,7 +22,10 @@ columns 5n+1 .. 5n+4 hold c_n0 .. c_n3. Per-orbital features:
     2  e_LUMO - e_HOMO            the gap (same for every orbital)
     3  +1 occupied, -1 virtual
     4..7   U_n[x, x] / s_n
-    8..11  log s_n
+    8  log(s_1 / s_0)   9  log(s_2 / s_0)   10  log(s_3 / s_2)
+    11 (e_x - mu0) / gap
+(no absolute scale of the moments enters, so the features do not drift with
+the size of the system)
 The network: three linear maps with GELU after the first two,
     Z1 = X W1 + b1, A1 = gelu(Z1), Z2 = A1 W2 + b2, A2 = gelu(Z2),
     Y = A2 W3 + b3,
@@ -89,7 +92,10 @@ def features(e_mf, nocc, m0):
     X[:, 3] = np.where(np.arange(N) < nocc, 1.0, -1.0)
     for n in range(NMOM):
         X[:, 4 + n] = np.diag(m0[n]) / s[n]
-        X[:, 8 + n] = np.log(s[n])
+    X[:, 8] = np.log(s[1] / s[0])
+    X[:, 9] = np.log(s[2] / s[0])
+    X[:, 10] = np.log(s[3] / s[2])
+    X[:, 11] = (e - mu0) / gap
     return X, s
 
 

@@ -269,10 +269,11 @@ __global__ __launch_bounds__(256) void features_kernel(int N, int nocc, const do
     f[2] = (float)gap;
     f[3] = x < nocc ? 1.0f : -1.0f;
 #pragma unroll
-    for (int n = 0; n < NMOM; ++n) {
-      f[4 + n] = (float)(m0[((long)n * N + x) * N + x] / s[n]);
-      f[8 + n] = (float)log(s[n]);
-    }
+    for (int n = 0; n < NMOM; ++n) f[4 + n] = (float)(m0[((long)n * N + x) * N + x] / s[n]);
+    f[8] = (float)log(s[1] / s[0]);
+    f[9] = (float)log(s[2] / s[0]);
+    f[10] = (float)log(s[3] / s[2]);
+    f[11] = (float)((e[x] - mu0) / gap);
   }
 }
 

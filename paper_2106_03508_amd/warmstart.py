@@ -33,7 +33,7 @@ from . import synthetic as syn
 
 PARAMS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_params.npy")
 
-TRAIN_SET = dict(n=500, seed0=10000, nmo_lo=40, nmo_hi=120)
+TRAIN_SET = dict(n=400, seed0=10000, nmo_lo=40, nmo_hi=160)
 HELDOUT_SET = dict(n=24, seed0=20000, nmo_lo=60, nmo_hi=160)
 
 
@@ -176,6 +176,7 @@ def evaluate(h, params, shapes, precs=("fp64",), exact=False):
         s = System(h, sh["seed"], sh["nmo"], sh["nocc"], sh["naux"])
         row = dict(seed=sh["seed"], nmo=sh["nmo"])
         cold = s.run(h)
+        log(f"  nmo={sh['nmo']} cold fp64: {cold['iterations']} iterations, {cold['wall_s']:.1f}s")
         row["cold"] = {q: cold[q] for q in ("iterations", "wall_s", "e_tot", "ip", "ea",
                                             "converged")}
         m0 = s.moments0(h)
@@ -185,12 +186,16 @@ def evaluate(h, params, shapes, precs=("fp64",), exact=False):
         t_pred = time.perf_counter() - t0
         for prec in precs:
             w = s.run(h, dm_init=dm, prec=prec)
+            log(f"  nmo={sh['nmo']} warm {prec}: {w['iterations']} iterations, "
+                f"{w['wall_s']:.1f}s")
             row[f"warm_{prec}"] = dict(
                 iterations=w["iterations"], wall_s=w["wall_s"] + t_pred, warm=w["warm"],
                 converged=w["converged"], d_ip=w["ip"] - cold["ip"], d_ea=w["ea"] - cold["ea"],
                 d_e=w["e_tot"] - cold["e_tot"])
             if prec != "fp64":
                 c2 = s.run(h, prec=prec)
+                log(f"  nmo={sh['nmo']} cold {prec}: {c2['iterations']} iterations, "
+                    f"{c2['wall_s']:.1f}s")
                 row[f"cold_{prec}"] = dict(
                     iterations=c2["iterations"], wall_s=c2["wall_s"],
                     d_ip=c2["ip"] - cold["ip"], d_ea=c2["ea"] - cold["ea"],

@@ -16,7 +16,7 @@ from paper_2106_03508_amd import synthetic as syn
 
 pytestmark = pytest.mark.gpu
 
-HELDOUT = dict(n=8, seed0=21000, nmo_lo=60, nmo_hi=110)
+HELDOUT = dict(n=8, seed0=21000, nmo_lo=80, nmo_hi=160)
 
 
 @pytest.fixture(scope="module")

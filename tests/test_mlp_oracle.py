@@ -124,7 +124,14 @@ def test_features_hand_case():
     assert np.allclose(X[:, 2], 1.5) and np.allclose(X[:, 3], [1, -1, -1])
     assert abs(s[0] - 6.25 / 3) < 1e-15
     assert np.allclose(X[:, 4], np.array([1.25, -1.75, 3.25]) / (6.25 / 3))
-    assert np.allclose(X[:, 8], np.log(6.25 / 3))
+    # moment n is (n + 1) diag(1, -2, 3) + 0.25: mean |diag| = (1.25 + 1.75 + 3.25) / 3
+    # for n = 0, (2.25 + 3.75 + 6.25) / 3 for n = 1, (3.25 + 5.75 + 9.25) / 3,
+    # (4.25 + 7.75 + 12.25) / 3
+    assert abs(s[1] - 12.25 / 3) < 1e-15 and abs(s[3] - 24.25 / 3) < 1e-15
+    assert np.allclose(X[:, 8], np.log(12.25 / 6.25))
+    assert np.allclose(X[:, 9], np.log(18.25 / 6.25))
+    assert np.allclose(X[:, 10], np.log(24.25 / 18.25))
+    assert np.allclose(X[:, 11], np.array([-0.75, 0.75, 2.25]) / 1.5)
 
 
 def test_zero_last_layer_gives_zero_correction():
