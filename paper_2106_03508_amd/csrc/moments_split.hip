@@ -163,14 +163,21 @@ struct XgemmArgs {
 
 constexpr int GT = 256;
 
+// One launch may carry two problems of the same inner size (the two mirrored
+// slabs of a block pair): workgroups [0, tiles0) take a0, the rest a1, so the
+// device does not idle between two partly filled rounds.
 template <bool F16>
-__global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmArgs a) {
+__global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmArgs a0, XgemmArgs a1,
+                                                         int tiles0) {
   // two stages (double buffer) x (hi, lo): 160 KiB, the whole LDS of a CU
   __shared__ u16x8 sA[2][2][GT][KVP];
   __shared__ u16x8 sB[2][2][GT][KVP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long G = (long)a.tiles_m * a.tiles_n;
-  const long logical = xcd_remap(blockIdx.x, G);
+  const long G = (long)gridDim.x;
+  long logical = xcd_remap(blockIdx.x, G);
+  const bool second = logical >= tiles0;
+  const XgemmArgs& a = second ? a1 : a0;
+  if (second) logical -= tiles0;
   const int tm = (int)(logical / a.tiles_n), tn = (int)(logical % a.tiles_n);
   const int m0 = tm * GT, n0 = tn * GT;
   const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -608,7 +615,7 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
   double* part = h.ws_moments[5].as<double>(part_stride * nsplit_max);
   AGF2_HIP(hipMemsetAsync(part, 0, part_stride * nsplit_max * sizeof(double), st));
 
-  auto gemm = [&](int prow, int nrow, int pcol, int ncol, float* C) {
+  auto problem = [&](int prow, int nrow, int pcol, int ncol, float* C) {
     XgemmArgs g;
     g.Ah = Rh + (long)prow * sRp; g.Al = Rl + (long)prow * sRp; g.sAp = sRp; g.sAx = sRx; g.mA = N;
     g.Bh = Sh + (long)pcol * sSp; g.Bl = Sl + (long)pcol * sSp; g.sBq = sSp; g.sBc = sSc;
@@ -616,10 +623,21 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
     g.M = nrow * N; g.Nn = ncol * nc; g.Qs = Qs;
     g.C = C; g.ldc = (long)ncol * nc;
     g.tiles_m = (g.M + GT - 1) / GT; g.tiles_n = (g.Nn + GT - 1) / GT;
-    ProfScope ps(h, "moments.slab", 2.0 * g.M * (double)g.Nn * Q,
-                 4.0 * ((double)g.M + g.Nn) * Qs + 4.0 * (double)g.M * g.Nn);
-    hipLaunchKernelGGL((xgemm_split_kernel<F16>), dim3((unsigned)((long)g.tiles_m * g.tiles_n)),
-                       dim3(NT), 0, st, g);
+    return g;
+  };
+  // one launch for one or two problems (the second may be null)
+  auto gemm = [&](const XgemmArgs& g0, const XgemmArgs* g1) {
+    const long t0 = (long)g0.tiles_m * g0.tiles_n;
+    const long t1 = g1 ? (long)g1->tiles_m * g1->tiles_n : 0;
+    double fl = 2.0 * g0.M * (double)g0.Nn * Q, by = 4.0 * ((double)g0.M + g0.Nn) * Qs +
+                                                     4.0 * (double)g0.M * g0.Nn;
+    if (g1) {
+      fl += 2.0 * g1->M * (double)g1->Nn * Q;
+      by += 4.0 * ((double)g1->M + g1->Nn) * Qs + 4.0 * (double)g1->M * g1->Nn;
+    }
+    ProfScope ps(h, "moments.slab", fl, by);
+    hipLaunchKernelGGL((xgemm_split_kernel<F16>), dim3((unsigned)(t0 + t1)), dim3(NT), 0, st,
+                       g0, g1 ? *g1 : g0, (int)t0);
     AGF2_CHECK_LAUNCH();
   };
 
@@ -628,8 +646,13 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
     for (int jb = ib; jb < nblk; ++jb, ++chunk) {
       const int P0 = ib * kb, na = std::min(kb, np - P0);
       const int P1 = jb * kb, nb = std::min(kb, np - P1);
-      gemm(P0, na, P1, nb, X1);
-      if (ib != jb) gemm(P1, nb, P0, na, X2);
+      const XgemmArgs g1 = problem(P0, na, P1, nb, X1);
+      if (ib != jb) {
+        const XgemmArgs g2 = problem(P1, nb, P0, na, X2);
+        gemm(g1, &g2);
+      } else {
+        gemm(g1, nullptr);
+      }
       const long first = chunk_first[chunk];
       const long last = (chunk + 1 < (int)chunk_first.size()) ? chunk_first[chunk + 1] : npairs;
       const long Kc = chunk_cols[chunk];
