@@ -163,21 +163,28 @@ struct XgemmArgs {
 
 constexpr int GT = 256;
 
-// One launch may carry two problems of the same inner size (the two mirrored
-// slabs of a block pair): workgroups [0, tiles0) take a0, the rest a1, so the
-// device does not idle between two partly filled rounds.
+// One launch carries up to XB problems of the same inner size (the mirrored
+// slabs of several block pairs): problem k owns workgroups [start[k],
+// start[k+1]), so the device does not idle between partly filled rounds.
+constexpr int XB = 8;
+struct XgemmBatch {
+  XgemmArgs p[XB];
+  int start[XB + 1];
+  int n;
+};
+
 template <bool F16>
-__global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmArgs a0, XgemmArgs a1,
-                                                         int tiles0) {
+__global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmBatch b) {
   // two stages (double buffer) x (hi, lo): 160 KiB, the whole LDS of a CU
   __shared__ u16x8 sA[2][2][GT][KVP];
   __shared__ u16x8 sB[2][2][GT][KVP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long G = (long)gridDim.x;
   long logical = xcd_remap(blockIdx.x, G);
-  const bool second = logical >= tiles0;
-  const XgemmArgs& a = second ? a1 : a0;
-  if (second) logical -= tiles0;
+  int k = 0;
+  while (k + 1 < b.n && logical >= b.start[k + 1]) ++k;
+  const XgemmArgs& a = b.p[k];
+  logical -= b.start[k];
   const int tm = (int)(logical / a.tiles_n), tn = (int)(logical % a.tiles_n);
   const int m0 = tm * GT, n0 = tn * GT;
   const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -603,10 +610,10 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
   kcap = (kcap + KS - 1) / KS * KS;
   u16* Z = h.ws_moments[4].as<u16>(4L * N * kcap);
   u16 *Zh = Z, *Zl = Z + (long)N * kcap, *Wh = Z + 2L * N * kcap, *Wl = Z + 3L * N * kcap;
+  // slab buffers: the two mirrored slabs of each of CB block pairs per launch
+  constexpr int CB = XB / 2;
   const long xel = (long)kb * N * (long)kb * nc;
-  float* X = reinterpret_cast<float*>(h.ws_moments[3].as<double>(xel + 8));   // X1, X2
-  float* X1 = X;
-  float* X2 = X + xel;
+  float* X = reinterpret_cast<float*>(h.ws_moments[3].as<double>(CB * xel + 8));
 
   const int tiles_n = (N + TS - 1) / TS;
   const int nlower = tiles_n * (tiles_n + 1) / 2;
@@ -625,34 +632,49 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
     g.tiles_m = (g.M + GT - 1) / GT; g.tiles_n = (g.Nn + GT - 1) / GT;
     return g;
   };
-  // one launch for one or two problems (the second may be null)
-  auto gemm = [&](const XgemmArgs& g0, const XgemmArgs* g1) {
-    const long t0 = (long)g0.tiles_m * g0.tiles_n;
-    const long t1 = g1 ? (long)g1->tiles_m * g1->tiles_n : 0;
-    double fl = 2.0 * g0.M * (double)g0.Nn * Q, by = 4.0 * ((double)g0.M + g0.Nn) * Qs +
-                                                     4.0 * (double)g0.M * g0.Nn;
-    if (g1) {
-      fl += 2.0 * g1->M * (double)g1->Nn * Q;
-      by += 4.0 * ((double)g1->M + g1->Nn) * Qs + 4.0 * (double)g1->M * g1->Nn;
+  // one launch for the problems collected in b
+  auto gemm = [&](XgemmBatch& b) {
+    double fl = 0.0, by = 0.0;
+    b.start[0] = 0;
+    for (int k = 0; k < b.n; ++k) {
+      const XgemmArgs& g = b.p[k];
+      b.start[k + 1] = b.start[k] + g.tiles_m * g.tiles_n;
+      fl += 2.0 * g.M * (double)g.Nn * Q;
+      by += 4.0 * ((double)g.M + g.Nn) * Qs + 4.0 * (double)g.M * g.Nn;
+    }
+    for (int k = b.n; k < XB; ++k) {
+      b.p[k] = b.p[0];
+      b.start[k + 1] = b.start[b.n];
     }
     ProfScope ps(h, "moments.slab", fl, by);
-    hipLaunchKernelGGL((xgemm_split_kernel<F16>), dim3((unsigned)(t0 + t1)), dim3(NT), 0, st,
-                       g0, g1 ? *g1 : g0, (int)t0);
+    hipLaunchKernelGGL((xgemm_split_kernel<F16>), dim3((unsigned)b.start[b.n]), dim3(NT), 0, st,
+                       b);
     AGF2_CHECK_LAUNCH();
   };
 
-  int chunk = 0;
+  std::vector<std::pair<int, int>> blocks;   // (ib, jb) in chunk order
   for (int ib = 0; ib < nblk; ++ib)
-    for (int jb = ib; jb < nblk; ++jb, ++chunk) {
+    for (int jb = ib; jb < nblk; ++jb) blocks.push_back({ib, jb});
+  const int nchunks = (int)blocks.size();
+  for (int c0 = 0; c0 < nchunks; c0 += CB) {
+    const int c1 = std::min(nchunks, c0 + CB);
+    XgemmBatch b;
+    b.n = 0;
+    for (int chunk = c0; chunk < c1; ++chunk) {
+      const int ib = blocks[chunk].first, jb = blocks[chunk].second;
       const int P0 = ib * kb, na = std::min(kb, np - P0);
       const int P1 = jb * kb, nb = std::min(kb, np - P1);
-      const XgemmArgs g1 = problem(P0, na, P1, nb, X1);
-      if (ib != jb) {
-        const XgemmArgs g2 = problem(P1, nb, P0, na, X2);
-        gemm(g1, &g2);
-      } else {
-        gemm(g1, nullptr);
-      }
+      float* X1 = X + 2L * (chunk - c0) * xel;
+      b.p[b.n++] = problem(P0, na, P1, nb, X1);
+      if (ib != jb) b.p[b.n++] = problem(P1, nb, P0, na, X1 + xel);
+    }
+    gemm(b);
+    for (int chunk = c0; chunk < c1; ++chunk) {
+      const int ib = blocks[chunk].first, jb = blocks[chunk].second;
+      const int P0 = ib * kb, na = std::min(kb, np - P0);
+      const int P1 = jb * kb, nb = std::min(kb, np - P1);
+      const float* X1 = X + 2L * (chunk - c0) * xel;
+      const float* X2 = X1 + xel;
       const long first = chunk_first[chunk];
       const long last = (chunk + 1 < (int)chunk_first.size()) ? chunk_first[chunk + 1] : npairs;
       const long Kc = chunk_cols[chunk];
@@ -694,6 +716,7 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
         AGF2_CHECK_LAUNCH();
       }
     }
+  }
   ProfScope ps(h, "moments.reduce", 0.0, 8.0 * (2.0 * nsplit_max + 2.0) * nn);
   reduce_moment_partials(part, part_stride, nsplit_max, N, U0, U1, st);
 }
