@@ -282,44 +282,88 @@ struct PairArgs {
   u16* Zh; u16* Zl; u16* Wh; u16* Wl; long ldz;
 };
 
-// Grid: (element blocks of N * nc, pairs); one workgroup row per pole pair.
+// Z column values of one (pair, x, c): the P column sqrt(1/2)(x1 + x2) and
+// the M column sqrt(3/2)(x1 - x2) (only x1 for p = q), each with its weighted
+// copy, as 16-bit pairs: out = {Zh, Zl, Wh, Wl} of P, then of M.
 template <bool F16>
-__global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
+__device__ __forceinline__ void pair_values(float x1, float x2, bool diag, float wgt,
+                                            float zscale, float wscale, u16 out[8]) {
   // sqrt(1/2) and sqrt(3/2) as float pairs: every column is multiplied with
   // one rounding (fma), so the constants' own float rounding does not bias
   // all P or all M columns alike
   const float cp_hi = 0.707106769084930419921875f, cp_lo = 1.2101617485882343e-08f;
   const float cm_hi = 1.22474491596221923828125f, cm_lo = -4.4570629853524224e-08f;
+  float zp = x1, zm = 0.f;
+  if (!diag) {
+    const float sp = x1 + x2, sm = x1 - x2;
+    zp = fmaf(sp, cp_hi, sp * cp_lo);
+    zm = fmaf(sm, cm_hi, sm * cm_lo);
+  }
+  split<F16>(zscale * zp, out[0], out[1]);
+  split<F16>(wscale * (wgt * zp), out[2], out[3]);
+  split<F16>(zscale * zm, out[4], out[5]);
+  split<F16>(wscale * (wgt * zm), out[6], out[7]);
+}
+
+// Grid: (element blocks, pairs); one workgroup row per pole pair. With V = 2
+// a thread takes two adjacent inner poles c, c+1 (nc even: the slab reads are
+// 8-byte and the Z stores 4-byte aligned, since pair column offsets are
+// multiples of nc and Z rows are multiples of 32 long).
+template <bool F16, int V>
+__global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
   const int pr = blockIdx.y;
   const int p = a.pa[pr], q = a.pb[pr];
+  const bool diag = (p == q);
   const long colbase = a.pcol[pr] - a.col_base;
-  const int per = a.N * a.nc;
+  const int ncv = a.nc / V;
+  const int per = a.N * ncv;
+  const float* r1 = a.X1 + (long)(p - a.P0) * a.N * a.ld1 + (long)(q - a.P1) * a.nc;
+  const float* r2 = (a.P0 == a.P1)
+                        ? a.X1 + (long)(q - a.P0) * a.N * a.ld1 + (long)(p - a.P1) * a.nc
+                        : a.X2 + (long)(q - a.P1) * a.N * a.ld2 + (long)(p - a.P0) * a.nc;
+  const long ld2 = (a.P0 == a.P1) ? a.ld1 : a.ld2;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < per; e += gridDim.x * 256) {
-    const int x = e / a.nc, c = e - x * a.nc;
+    const int x = e / ncv, c = V * (e - x * ncv);
     const long o = (long)x * a.ldz + colbase + c;
-    float x1 = a.X1[((long)(p - a.P0) * a.N + x) * a.ld1 + (long)(q - a.P1) * a.nc + c];
-    if constexpr (F16)
-      x1 = ldexpf(x1, a.eR[p] + a.eS[(long)q * a.sEp + (long)c * a.sEc] - 2 * EMAX);
-    const float wgt = (float)(a.ep[p] + a.ep[q] - a.ec[c]);
-    u16 h, l;
-    if (p == q) {
-      split<F16>(a.zscale * x1, h, l); a.Zh[o] = h; a.Zl[o] = l;
-      split<F16>(a.wscale * (wgt * x1), h, l); a.Wh[o] = h; a.Wl[o] = l;
-      continue;
+    float x1[V], x2[V];
+    if constexpr (V == 2) {
+      const float2 v1 = *reinterpret_cast<const float2*>(r1 + (long)x * a.ld1 + c);
+      x1[0] = v1.x; x1[1] = v1.y;
+      if (!diag) {
+        const float2 v2 = *reinterpret_cast<const float2*>(r2 + (long)x * ld2 + c);
+        x2[0] = v2.x; x2[1] = v2.y;
+      } else {
+        x2[0] = x2[1] = 0.f;
+      }
+    } else {
+      x1[0] = r1[(long)x * a.ld1 + c];
+      x2[0] = diag ? 0.f : r2[(long)x * ld2 + c];
     }
-    float x2 = (a.P0 == a.P1)
-                   ? a.X1[((long)(q - a.P0) * a.N + x) * a.ld1 + (long)(p - a.P1) * a.nc + c]
-                   : a.X2[((long)(q - a.P1) * a.N + x) * a.ld2 + (long)(p - a.P0) * a.nc + c];
-    if constexpr (F16)
-      x2 = ldexpf(x2, a.eR[q] + a.eS[(long)p * a.sEp + (long)c * a.sEc] - 2 * EMAX);
-    const float sp = x1 + x2, sm = x1 - x2;
-    const float zp = fmaf(sp, cp_hi, sp * cp_lo);
-    const float zm = fmaf(sm, cm_hi, sm * cm_lo);
-    split<F16>(a.zscale * zp, h, l); a.Zh[o] = h; a.Zl[o] = l;
-    split<F16>(a.wscale * (wgt * zp), h, l); a.Wh[o] = h; a.Wl[o] = l;
-    const long om = o + a.nc;
-    split<F16>(a.zscale * zm, h, l); a.Zh[om] = h; a.Zl[om] = l;
-    split<F16>(a.wscale * (wgt * zm), h, l); a.Wh[om] = h; a.Wl[om] = l;
+    u16 v[V][8];
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+      const int cc = c + t;
+      if constexpr (F16) {
+        x1[t] = ldexpf(x1[t], a.eR[p] + a.eS[(long)q * a.sEp + (long)cc * a.sEc] - 2 * EMAX);
+        if (!diag)
+          x2[t] = ldexpf(x2[t], a.eR[q] + a.eS[(long)p * a.sEp + (long)cc * a.sEc] - 2 * EMAX);
+      }
+      const float wgt = (float)(a.ep[p] + a.ep[q] - a.ec[cc]);
+      pair_values<F16>(x1[t], x2[t], diag, wgt, a.zscale, a.wscale, v[t]);
+    }
+    u16* dst[4] = {a.Zh, a.Zl, a.Wh, a.Wl};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if constexpr (V == 2) {
+        *reinterpret_cast<unsigned*>(dst[k] + o) = (unsigned)v[0][k] | ((unsigned)v[1][k] << 16);
+        if (!diag)
+          *reinterpret_cast<unsigned*>(dst[k] + o + a.nc) =
+              (unsigned)v[0][4 + k] | ((unsigned)v[1][4 + k] << 16);
+      } else {
+        dst[k][o] = v[0][k];
+        if (!diag) dst[k][o + a.nc] = v[0][4 + k];
+      }
+    }
   }
 }
 
@@ -690,12 +734,13 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
       {
         const long tot = (long)pa.npairs * N * nc;
         ProfScope ps(h, "moments.pair", 0.0, 4.0 * 2.0 * tot + 8.0 * N * (double)Kc);
-        const long per = (long)N * nc;
-        AGF2_REQUIRE(per < (1L << 31) - 256 && pa.npairs <= 65535, "pair chunk too large");
-        hipLaunchKernelGGL((pair_split_kernel<F16>),
-                           dim3((unsigned)std::min<long>((per + 255) / 256, 16384),
-                                (unsigned)pa.npairs),
-                           dim3(256), 0, st, pa);
+        const bool two = (nc % 2 == 0) && (kcap % 2 == 0);
+        const long per = (long)N * nc / (two ? 2 : 1);
+        AGF2_REQUIRE((long)N * nc < (1L << 31) - 256 && pa.npairs <= 65535,
+                     "pair chunk too large");
+        const dim3 grid((unsigned)std::min<long>((per + 255) / 256, 16384), (unsigned)pa.npairs);
+        if (two) hipLaunchKernelGGL((pair_split_kernel<F16, 2>), grid, dim3(256), 0, st, pa);
+        else hipLaunchKernelGGL((pair_split_kernel<F16, 1>), grid, dim3(256), 0, st, pa);
         AGF2_CHECK_LAUNCH();
       }
       int nsplit = choose_splits(Kc, nlower, nsplit_max,
