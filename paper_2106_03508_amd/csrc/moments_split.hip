@@ -151,8 +151,8 @@ __global__ void split_rows_kernel(const double* in, long s_in_a, long s_in_b, in
 // Slab as a plain tiled GEMM over blocks of poles:
 //   X[(p, x)][(q, c)] = sum_Q R[p][x][Q] S[q][c][Q]
 // for p in a row block and q in a column block, with rows and columns
-// addressed through (pole, index) pairs. 256x256 output tiles, four waves of
-// 128x128 (8x8 MFMA blocks each), float32 accumulators.
+// addressed through (pole, index) pairs. 256x256 output tiles, eight waves of
+// 128x64 (8x4 MFMA blocks each, two waves per SIMD), float32 accumulators.
 struct XgemmArgs {
   const u16* Ah; const u16* Al; long sAp, sAx; int mA;   // row m: (m / mA) sAp + (m % mA) sAx
   const u16* Bh; const u16* Bl; long sBq, sBc; int nB;   // row n: (n / nB) sBq + (n % nB) sBc
@@ -173,8 +173,13 @@ struct XgemmBatch {
   int n;
 };
 
+// Eight waves (two per SIMD) share one 256 x 256 output tile, each wave a
+// 128 x 64 block of 8 x 4 MFMA tiles, so a SIMD can issue one wave's MFMAs
+// while the other waits on LDS or global memory.
+constexpr int XNT = 512;
+
 template <bool F16>
-__global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmBatch b) {
+__global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
   // two stages (double buffer) x (hi, lo): 160 KiB, the whole LDS of a CU
   __shared__ u16x8 sA[2][2][GT][KVP];
   __shared__ u16x8 sB[2][2][GT][KVP];
@@ -188,43 +193,43 @@ __global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmBatch b) {
   const int tm = (int)(logical / a.tiles_n), tn = (int)(logical % a.tiles_n);
   const int m0 = tm * GT, n0 = tn * GT;
   const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-  // loader: per operand 256 rows x 4 vectors; thread -> rows tid/4 + 64 i, vector tid % 4
+  // loader: per operand 256 rows x 4 vectors; thread -> rows tid/4 + 128 i, vector tid % 4
   const int kv = tid & 3;
-  long oa[4], ob[4];
+  long oa[2], ob[2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = (tid >> 2) + 64 * i;
+  for (int i = 0; i < 2; ++i) {
+    const int r = (tid >> 2) + 128 * i;
     const int m = m0 + r, n = n0 + r;
     oa[i] = m < a.M ? (long)(m / a.mA) * a.sAp + (long)(m % a.mA) * a.sAx + 8 * kv : -1;
     ob[i] = n < a.Nn ? (long)(n / a.nB) * a.sBq + (long)(n % a.nB) * a.sBc + 8 * kv : -1;
   }
-  u16x8 pa[8], pb[8];
+  u16x8 pa[4], pb[4];
   auto load = [&](int kb) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i) {
       pa[i] = oa[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Ah + oa[i] + kb) : zero8;
-      pa[4 + i] = oa[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Al + oa[i] + kb) : zero8;
+      pa[2 + i] = oa[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Al + oa[i] + kb) : zero8;
       pb[i] = ob[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Bh + ob[i] + kb) : zero8;
-      pb[4 + i] = ob[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Bl + ob[i] + kb) : zero8;
+      pb[2 + i] = ob[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Bl + ob[i] + kb) : zero8;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = (tid >> 2) + 64 * i;
+    for (int i = 0; i < 2; ++i) {
+      const int r = (tid >> 2) + 128 * i;
       sA[buf][0][r][kv] = pa[i];
-      sA[buf][1][r][kv] = pa[4 + i];
+      sA[buf][1][r][kv] = pa[2 + i];
       sB[buf][0][r][kv] = pb[i];
-      sB[buf][1][r][kv] = pb[4 + i];
+      sB[buf][1][r][kv] = pb[2 + i];
     }
   };
   const int fr = lane & 15, fk = lane >> 4;
-  const int wm = (wave & 1) * 128, wn = (wave >> 1) * 128;
-  f4 acc[8][8];
+  const int wm = (wave & 1) * 128, wn = (wave >> 1) * 64;
+  f4 acc[8][4];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int nsteps = a.Qs / KS;
   // stage k lives in buffer k & 1: the next stage's global loads are issued
   // before this stage's MFMAs and written to the other buffer after them, so
@@ -242,7 +247,7 @@ __global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmBatch b) {
       al[i] = sA[buf][1][wm + 16 * i + fr][fk];
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < 4; ++j) {
       const u16x8 bh = sB[buf][0][wn + 16 * j + fr][fk], bl = sB[buf][1][wn + 16 * j + fr][fk];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
@@ -257,7 +262,7 @@ __global__ __launch_bounds__(NT) void xgemm_split_kernel(XgemmBatch b) {
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + crow(lane, r);
@@ -691,7 +696,7 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
       b.start[k + 1] = b.start[b.n];
     }
     ProfScope ps(h, "moments.slab", fl, by);
-    hipLaunchKernelGGL((xgemm_split_kernel<F16>), dim3((unsigned)b.start[b.n]), dim3(NT), 0, st,
+    hipLaunchKernelGGL((xgemm_split_kernel<F16>), dim3((unsigned)b.start[b.n]), dim3(XNT), 0, st,
                        b);
     AGF2_CHECK_LAUNCH();
   };
