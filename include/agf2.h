@@ -141,7 +141,10 @@ agf2_status agf2_compress(agf2_handle_t handle, int nphys, const double* m0,
 /* Options of the Fock loop. */
 typedef struct {
   double tol_rdm1;    /* stop when ||change of the density||_F is below     */
-  double tol_nelec;   /* |electron count - nelec| target of the shift fit   */
+  double tol_nelec;   /* |electron count - nelec| target of the shift fit
+                         once the density has settled (a cycle fits to
+                         max(tol_nelec, min(1e-6, 0.01 x the previous
+                         cycle's density change)))                          */
   double bracket;     /* largest shift step tried, Ha                        */
   double step0;       /* first shift step of the bracket search, Ha          */
   int max_cycle;      /* density cycles                                      */

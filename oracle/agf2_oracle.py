@@ -462,17 +462,32 @@ def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
     converged = False
     diis = DIIS(diis_space) if diis_space else None
     N = F.shape[0]
+    err_prev = np.inf
     for cycle in range(1, max_cycle + 1):
+        # the electron count is fitted to tol_nelec once the density has
+        # settled; earlier cycles, whose density is still moving, to
+        # 0.01 x its last change (at most 1e-6)
+        tol_c = max(tol_nelec, min(1e-6, 1e-2 * err_prev))
         shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift,
-                              bracket=bracket, tol=tol_nelec)
+                              bracket=bracket, tol=tol_c)
         n_eig += ne
         lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
         n_eig += 1
         uo = u[:, :n]
         D_new = 2.0 * uo @ uo.T
         err = np.linalg.norm(D_new - D)
+        err_prev = err
         D = D_new
         if err < tol_rdm1:
+            if tol_c > tol_nelec:
+                # the returned density meets tol_nelec (same F)
+                shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift,
+                                      bracket=bracket, tol=tol_nelec)
+                n_eig += ne
+                lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
+                n_eig += 1
+                uo = u[:, :n]
+                D = 2.0 * uo @ uo.T
             converged = True
             break
         F_new = fock_matrix(h, L, D)

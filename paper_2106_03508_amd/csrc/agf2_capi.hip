@@ -382,14 +382,14 @@ struct FockLoop {
   // common shift of the auxiliary energies giving the right electron count:
   // bracket by doubling steps, then Illinois regula falsi (count is
   // non-decreasing in the shift for a fixed number of occupied poles).
-  double fit_shift(const double* F, double shift0, const agf2_fock_opts& o) {
+  double fit_shift(const double* F, double shift0, const agf2_fock_opts& o, double tol) {
     Aufbau a = solve(F, shift0);
     double shift = shift0;
     int nocc = a.n;
     double cnt = a.count;
     for (int rep = 0; rep < 8; ++rep) {
       const double g0 = cnt - nelec;
-      if (std::fabs(g0) < o.tol_nelec) return shift;
+      if (std::fabs(g0) < tol) return shift;
       auto g = [&](double d) {
         solve(F, d);
         return count_n(nocc) - nelec;
@@ -415,7 +415,7 @@ struct FockLoop {
           if (gb == 0.0) { x = b; break; }
           x = b - gb * (b - a_) / (gb - ga);
           const double gx = g(x);
-          if (std::fabs(gx) < o.tol_nelec) break;
+          if (std::fabs(gx) < tol) break;
           if ((gx > 0) == (gb > 0)) {
             b = x; gb = gx;
             if (side == -1) ga *= 0.5;
@@ -536,24 +536,40 @@ FockLoopResult fock_loop_impl(Handle& h, int nphys, int naux, const double* Lpq,
   bool converged = false;
   int cycle = 0;
   Aufbau a;
+  double err_prev = INFINITY;
   for (cycle = 1; cycle <= o.max_cycle; ++cycle) {
-    d = fl.fit_shift(F, d, o);
-    if (!(fl.solved_shift == d && fl.solved_F == F)) fl.solve(F, d);
-    a = aufbau(fl.n, fl.hlam, fl.hw, (double)nelec);
-    // D = 2 sum_{l < n*} phi_l phi_l^T (physical block)
-    Gemm g;
-    g.M = N; g.N = N; g.K = a.n;
-    g.A = fl.H; g.sAm = 1; g.sAk = fl.n;
-    g.B = fl.H; g.sBn = 1; g.sBk = fl.n;
-    g.C = Dn; g.sCm = N; g.sCn = 1; g.alpha = 2.0;
-    if (a.n > 0) gemm_f64(g, s);
-    else AGF2_HIP(hipMemsetAsync(Dn, 0, nn * sizeof(double), s));
+    // the electron count is fitted to tol_nelec once the density has
+    // settled; earlier cycles, whose density is still moving, to 0.01 x its
+    // last change (at most 1e-6)
+    const double tol_c = std::max(o.tol_nelec, std::min(1e-6, 1e-2 * err_prev));
+    // fit the shift at F to tolerance tol, then D = 2 sum_{l < n*} phi_l phi_l^T
+    // (physical block) into Dn
+    auto fit_and_density = [&](double tol) {
+      d = fl.fit_shift(F, d, o, tol);
+      if (!(fl.solved_shift == d && fl.solved_F == F)) fl.solve(F, d);
+      a = aufbau(fl.n, fl.hlam, fl.hw, (double)nelec);
+      Gemm g;
+      g.M = N; g.N = N; g.K = a.n;
+      g.A = fl.H; g.sAm = 1; g.sAk = fl.n;
+      g.B = fl.H; g.sBn = 1; g.sBk = fl.n;
+      g.C = Dn; g.sCm = N; g.sCn = 1; g.alpha = 2.0;
+      if (a.n > 0) gemm_f64(g, s);
+      else AGF2_HIP(hipMemsetAsync(Dn, 0, nn * sizeof(double), s));
+    };
+    fit_and_density(tol_c);
     // Frobenius norm of the change of D
     hipLaunchKernelGGL(sqdiff_kernel, dim3(nblk(nn)), dim3(256), 0, s, nn, Dn, rdm1, Fn);
     AGF2_CHECK_LAUNCH();
     const double err = std::sqrt(dot_f64(h, nn, Fn, Fn));
+    err_prev = err;
+    if (err < o.tol_rdm1) {
+      // converged: the returned density meets tol_nelec (same F, so no new J/K)
+      if (tol_c > o.tol_nelec) fit_and_density(o.tol_nelec);
+      AGF2_HIP(hipMemcpyAsync(rdm1, Dn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+      converged = true;
+      break;
+    }
     AGF2_HIP(hipMemcpyAsync(rdm1, Dn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (err < o.tol_rdm1) { converged = true; break; }
     fock_build(h, N, naux, Lpq, hcore, rdm1, 1.0, Fn);
     // error vector F[D] - F, stored in Dn (free now)
     hipLaunchKernelGGL(sqdiff_kernel, dim3(nblk(nn)), dim3(256), 0, s, nn, Fn, F, Dn);
