@@ -126,55 +126,55 @@ void fock_build(Handle& h, int N, int Q, const double* L, const double* hcore,
                 const double* D, double alpha, double* F) {
   hipStream_t st = h.stream;
   const long nn = (long)N * N;
-  ProfScope ps(h, "fock.jk", 3.0 * Q * (double)nn * N + 4.0 * Q * (double)nn,
+  ProfScope ps(h, "fock.jk", 4.0 * Q * (double)nn * N + 4.0 * Q * (double)nn,
                8.0 * (3.0 * Q * nn + 3.0 * nn));
   double* rho = h.ws_fock[0].as<double>(Q);
   hipLaunchKernelGGL(rho_kernel, dim3(Q), dim3(RT), 0, st, L, D, N, rho);
   AGF2_CHECK_LAUNCH();
-  // exchange K[p][q] = sum_Q (L_Q D L_Q)[p][q], Q processed in chunks:
-  //   V[Q][p][r] = sum_s L[Q][p][s] D[s][r]; K += sum_{Q,r} V[Q][p][r] L[Q][r][q]
-  // The first product is a plain strided-batched GEMM (rocBLAS; column-major
-  // the memory of L_Q and D reads as themselves, both symmetric, and C = D L_Q
-  // stored column-major is L_Q D row-major). The second runs on the library's
-  // GEMM over the lower triangle only (K is symmetric), split over Q into
-  // fixed-order partials; the split count is the one whose whole rounds of
-  // resident workgroups give the least work per split (ties: fewer splits).
-  // (One rocBLAS GEMM with inner size qn N for the second product measured
-  // 1.7x slower at nmo=1000.)
-  const int tside = (int)std::lround(std::sqrt((double)gemm_f64_tiles(N, N)));
-  const long tlow = (long)tside * (tside + 1) / 2;
-  const int slots = gemm_f64_slots();
-  int nsplit = 1;
-  double best = 1e300;
-  for (int ns = 1; ns <= 32; ++ns) {
-    const double t = (double)((tlow * ns + slots - 1) / slots) / ns;
-    if (t < best - 1e-12) { best = t; nsplit = ns; }
-  }
+  // exchange K = sum_Q L_Q D L_Q, Q processed in chunks of qn slices, as
+  // plain products on rocBLAS (column-major view: the memory of L_Q and D reads
+  // as L_Q and D, both symmetric):
+  //   X_Q = D L_Q, stored stacked as rows Q*N .. Q*N+N-1 of one (qn N) x N
+  //         matrix (strided-batched GEMM);
+  //   P_g = [L_Q ...] [X_Q; ...] over the G slices of group g, one GEMM of
+  //         inner size G*N per group (strided-batched over the groups);
+  //   K   = sum of the group partials of all chunks (fixed order).
+  // Groups of about 8 slices keep each GEMM's inner size near 8N: one GEMM of
+  // inner size qn N measured 1.7x slower, the library's own lower-triangle
+  // GEMM reached ~25 TFLOP/s here.
   const long chunk_bytes = 1L << 30;
   const int QC = (int)std::max<long>(1, std::min<long>(Q, chunk_bytes / (8 * nn)));
-  double* V = h.ws_fock[1].as<double>((long)QC * nn);
-  double* Kp = h.ws_fock[2].as<double>((long)nsplit * nn);
+  const int GS = std::max(1, std::min(8, QC));           // slices per group
+  const int GMAX = (QC + GS - 1) / GS;                      // groups per chunk
+  double* X = h.ws_fock[1].as<double>((long)QC * nn);
+  double* Kp = h.ws_fock[2].as<double>((long)GMAX * nn);   // group k of every chunk adds to slot k
   double* K = h.ws_fock[3].as<double>(nn);
-  AGF2_HIP(hipMemsetAsync(Kp, 0, (long)nsplit * nn * sizeof(double), st));
+  auto check = [](rocblas_status bs, const char* what) {
+    if (bs != rocblas_status_success)
+      throw Error{AGF2_ERR_HIP, std::string(what) + ": " + rocblas_status_to_string(bs)};
+  };
   for (int q0 = 0; q0 < Q; q0 += QC) {
     const int qn = std::min(QC, Q - q0);
-    const double one = 1.0, zero = 0.0;
-    const rocblas_status bs = rocblas_dgemm_strided_batched(
-        h.blas, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, D, N, 0,
-        L + (long)q0 * nn, N, nn, &zero, V, N, nn, qn);
-    if (bs != rocblas_status_success)
-      throw Error{AGF2_ERR_HIP, std::string("rocblas_dgemm_strided_batched: ") +
-                                    rocblas_status_to_string(bs)};
-    Gemm g2;
-    g2.M = N; g2.N = N; g2.K = N; g2.R = qn; g2.nsplit = nsplit;
-    g2.A = V; g2.sAr = nn; g2.sAm = N; g2.sAk = 1;
-    g2.B = L + (long)q0 * nn; g2.sBr = nn; g2.sBk = N; g2.sBn = 1;
-    g2.C = Kp; g2.sCs = nn; g2.sCm = N; g2.sCn = 1;
-    g2.beta = 1.0;
-    g2.lower = true;
-    gemm_f64(g2, st);
+    const double one = 1.0, zero = 0.0, beta = q0 == 0 ? 0.0 : 1.0;   // chunk 0 has GMAX groups
+    const long ldx = (long)qn * N;
+    check(rocblas_dgemm_strided_batched(h.blas, rocblas_operation_none, rocblas_operation_none,
+                                        N, N, N, &one, D, N, 0, L + (long)q0 * nn, N, nn, &zero,
+                                        X, ldx, N, qn),
+          "rocblas_dgemm_strided_batched");
+    const int full = qn / GS, rest = qn - full * GS;
+    if (full > 0)
+      check(rocblas_dgemm_strided_batched(
+                h.blas, rocblas_operation_none, rocblas_operation_none, N, N, GS * N, &one,
+                L + (long)q0 * nn, N, (long)GS * nn, X, ldx, (long)GS * N, &beta, Kp, N, nn,
+                full),
+            "rocblas_dgemm_strided_batched");
+    if (rest > 0)
+      check(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none, N, N, rest * N,
+                          &one, L + (long)(q0 + full * GS) * nn, N, X + (long)full * GS * N, ldx,
+                          &beta, Kp + (long)full * nn, N),
+            "rocblas_dgemm");
   }
-  sum_slices(Kp, nn, nsplit, nn, K, 1.0, false, st);
+  sum_slices(Kp, nn, GMAX, nn, K, 1.0, false, st);
   hipLaunchKernelGGL(fock_combine_kernel, dim3(nblocks(nn)), dim3(256), 0, st, L, rho,
                      Q, N, hcore, K, alpha, F);
   AGF2_CHECK_LAUNCH();
