@@ -118,10 +118,17 @@ int grouped_grid_f64(int kind, int tc);
 void fill_zero(double* p, long n, hipStream_t st);
 void reduce_moment_partials(const double* part, long part_stride, int nsplit, int N,
                             double* U0, double* U1, hipStream_t st);
-void pole_transform_f64(Handle& h, int N, int Q, int Qp, const double* L, const double* u,
-                        int npole, int p0, int np, double* T);
+void pole_transform_f64(int N, int Q, int Qp, const double* L, const double* u, int npole,
+                        int p0, int np, double* T, hipStream_t st);
 void lov_transform_f64(int N, int Q, int Qp, const double* u, int npole, int o, int v,
                        const double* Lxv, double* Lov, hipStream_t st);
+// Library-GEMM versions on the handle's stream (not for graph capture).
+// Lov part: a in [0, na) of a chunk Txv[a][x][Qp] (stride sTa per a) into
+// Tov[i][a][Qp] with row stride na * Qp.
+void pole_transform_blas(Handle& h, int N, int Q, int Qp, const double* L, const double* u,
+                         int npole, int p0, int np, double* T);
+void lov_transform_blas(Handle& h, int N, int Q, int Qp, const double* u, int npole, int o,
+                        int na, const double* Txv, long sTa, double* Tov);
 void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
                        int nocc, const double* e, const double* u, double* m0o,
                        double* m1o, double* m0v, double* m1v);

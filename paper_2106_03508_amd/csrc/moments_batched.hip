@@ -89,15 +89,8 @@ struct Job {
 void transform_system(hipStream_t st, int N, int Q, int Qp, const double* L, const double* u,
                       int npole, int o, double* Lxo, double* Lxv, double* Lov) {
   const int v = npole - o;
-  for (int part = 0; part < 2; ++part) {
-    const int p0 = part == 0 ? 0 : o, np = part == 0 ? o : v;
-    Gemm g;
-    g.M = np; g.N = Q; g.K = N; g.batch = N;
-    g.A = u + p0; g.sAm = 1; g.sAk = npole;               // A(p, r) = u[r][p0+p]
-    g.B = L; g.sBb = N; g.sBk = 1; g.sBn = (long)N * N;   // B(r, Q) = L[Q][x][r]
-    g.C = part == 0 ? Lxo : Lxv; g.sCb = Qp; g.sCm = (long)N * Qp; g.sCn = 1;
-    gemm_f64_padded(g, Qp, st);
-  }
+  pole_transform_f64(N, Q, Qp, L, u, npole, 0, o, Lxo, st);
+  pole_transform_f64(N, Q, Qp, L, u, npole, o, v, Lxv, st);
   lov_transform_f64(N, Q, Qp, u, npole, o, v, Lxv, Lov, st);
 }
 

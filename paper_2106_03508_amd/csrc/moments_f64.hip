@@ -316,6 +316,27 @@ __global__ void fill_zero_kernel(double* p, long n) {
 
 inline long nblocks(long n) { return std::max<long>(1, std::min<long>((n + 255) / 256, 4096)); }
 
+// Zero columns [Q, Qp) of `rows` rows of length Qp (the padding the library
+// GEMMs leave unwritten).
+__global__ void zero_pad_kernel(double* T, long rows, int Q, int Qp) {
+  const int w = Qp - Q;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * w;
+       i += (long)gridDim.x * blockDim.x)
+    T[(i / w) * Qp + Q + i % w] = 0.0;
+}
+
+void zero_pad(double* T, long rows, int Q, int Qp, hipStream_t st) {
+  if (Qp == Q || rows == 0) return;
+  hipLaunchKernelGGL(zero_pad_kernel, dim3(nblocks(rows * (Qp - Q))), dim3(256), 0, st, T,
+                     rows, Q, Qp);
+  AGF2_CHECK_LAUNCH();
+}
+
+void blas_check(rocblas_status bs, const char* what) {
+  if (bs != rocblas_status_success)
+    throw Error{AGF2_ERR_HIP, std::string(what) + ": " + rocblas_status_to_string(bs)};
+}
+
 }  // namespace
 
 int slab_f64_tc(int nc) { return nc >= 48 ? 64 : (nc >= 24 ? 32 : 16); }
@@ -492,15 +513,62 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
 
 // Pole-basis DF tensors, Q padded to Qp (a multiple of 16) with zeros:
 //   T[p][x][Q] = sum_r u[r][p0+p] L[Q][x][r]          (p in [0, np))
-void pole_transform_f64(Handle& h, int N, int Q, int Qp, const double* L,
-                        const double* u, int npole, int p0, int np, double* T) {
+void pole_transform_f64(int N, int Q, int Qp, const double* L, const double* u, int npole,
+                        int p0, int np, double* T, hipStream_t st) {
   if (np == 0) return;
   Gemm g;
   g.M = np; g.N = Q; g.K = N; g.batch = N;
   g.A = u + p0; g.sAm = 1; g.sAk = npole;              // A(p, r) = u[r][p0+p]
   g.B = L; g.sBb = N; g.sBk = 1; g.sBn = (long)N * N;  // B(r, Q) = L[Q][x][r]
   g.C = T; g.sCb = Qp; g.sCm = (long)N * Qp; g.sCn = 1;
-  gemm_f64_padded(g, Qp, h.stream);
+  gemm_f64_padded(g, Qp, st);
+}
+
+// The same two transforms as strided-batched library GEMMs on the handle's
+// stream (column-major views; one GEMM per x, resp. per a):
+//   T[p][x][0:Q] = L[0:Q][x][:] u[:][p0+p]          m = Q, n = np, k = N
+//   Lov[i][a][0:Q] = Lxv[a][:][0:Q]^T u[:][i]         m = Q, n = o, k = N
+// with the padding columns [Q, Qp) zeroed. Each call is cut so that no
+// operand of one GEMM spans more than 2 GiB (ld x columns), which keeps every
+// in-matrix byte offset in 31 bits; the cuts are multiples of 128 rows and 64
+// columns where the bound allows.
+namespace {
+int cut(long per_unit_bytes, int total, int align) {
+  const long lim = (1L << 31) / std::max<long>(1, per_unit_bytes);
+  long c = lim >= align ? lim / align * align : std::max<long>(1, lim);
+  return (int)std::min<long>(total, c);
+}
+}  // namespace
+
+void pole_transform_blas(Handle& h, int N, int Q, int Qp, const double* L, const double* u,
+                         int npole, int p0, int np, double* T) {
+  if (np == 0) return;
+  const double one = 1.0, zero = 0.0;
+  const long nn = (long)N * N, ldc = (long)N * Qp;
+  const int qc = cut(8 * nn, Q, 128), pcut = cut(8 * ldc, np, 64);
+  for (int q0 = 0; q0 < Q; q0 += qc)
+    for (int c0 = 0; c0 < np; c0 += pcut)
+      blas_check(rocblas_dgemm_strided_batched(
+                     h.blas, rocblas_operation_transpose, rocblas_operation_transpose,
+                     std::min(qc, Q - q0), std::min(pcut, np - c0), N, &one, L + q0 * nn, nn,
+                     N, u + p0 + c0, npole, 0, &zero, T + c0 * ldc + q0, ldc, Qp, N),
+                 "rocblas_dgemm_strided_batched (pole transform)");
+  zero_pad(T, (long)np * N, Q, Qp, h.stream);
+}
+
+void lov_transform_blas(Handle& h, int N, int Q, int Qp, const double* u, int npole, int o,
+                        int na, const double* Txv, long sTa, double* Tov) {
+  if (o == 0 || na == 0) return;
+  const double one = 1.0, zero = 0.0;
+  const long ldc = (long)na * Qp;
+  const int icut = cut(8 * ldc, o, 64);
+  for (int i0 = 0; i0 < o; i0 += icut)
+    blas_check(rocblas_dgemm_strided_batched(
+                   h.blas, rocblas_operation_none, rocblas_operation_transpose, Q,
+                   std::min(icut, o - i0), N, &one, Txv, Qp, sTa, u + i0, npole, 0, &zero,
+                   Tov + i0 * ldc, ldc, Qp, na),
+               "rocblas_dgemm_strided_batched (Lov transform)");
+  zero_pad(Tov, (long)o * na, Q, Qp, h.stream);
 }
 
 // Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q]
@@ -527,9 +595,9 @@ void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
     ProfScope ps(h, "moments.transform",
                  2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
                  8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
-    pole_transform_f64(h, N, Q, Qp, L, u, npole, 0, o, Lxo);
-    pole_transform_f64(h, N, Q, Qp, L, u, npole, o, v, Lxv);
-    lov_transform_f64(N, Q, Qp, u, npole, o, v, Lxv, Lov, h.stream);
+    pole_transform_blas(h, N, Q, Qp, L, u, npole, 0, o, Lxo);
+    pole_transform_blas(h, N, Q, Qp, L, u, npole, o, v, Lxv);
+    lov_transform_blas(h, N, Q, Qp, u, npole, o, v, Lxv, (long)N * Qp, Lov);
   }
   // lesser: pairs (i, j) occupied, inner a virtual; S[j][a][Q] = Lov[j][a][Q]
   moments_part_f64(h, N, Q, Qp, Lxo, (long)N * Qp, Qp, Lov, (long)v * Qp, Qp,

@@ -27,8 +27,6 @@ namespace agf2 {
 
 void reduce_moment_partials(const double* part, long part_stride, int nsplit, int N,
                             double* U0, double* U1, hipStream_t st);
-void pole_transform_f64(Handle& h, int N, int Q, int Qp, const double* L, const double* u,
-                        int npole, int p0, int np, double* T);
 
 namespace {
 
@@ -822,14 +820,14 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
     ProfScope ps(h, "moments.transform",
                  2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
                  8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
-    // float64 staging in chunks of poles (<= ~1 GiB each)
+    // float64 staging in chunks of poles (<= ~4 GiB each)
     const long per_pole = (long)N * Qp;
-    const int pc = (int)std::max<long>(1, std::min<long>(npole, (1L << 27) / per_pole));
+    const int pc = (int)std::max<long>(1, std::min<long>(npole, (1L << 29) / per_pole));
     double* T = h.ws_moments[3].as<double>((long)pc * per_pole + (long)o * pc * Qp);
     double* Tov = T + (long)pc * per_pole;
     for (int p0 = 0; p0 < o; p0 += pc) {
       const int np = std::min(pc, o - p0);
-      pole_transform_f64(h, N, Q, Qp, L, u, npole, p0, np, T);
+      pole_transform_blas(h, N, Q, Qp, L, u, npole, p0, np, T);
       // rows (p, x); one exponent per pole p
       if (F16) row_stats(T, per_pole, Qp, np, N, Q, 1, 0, eRo + p0, nrm + 0, st);
       split_rows<F16>(T, per_pole, Qp, np, N, perm, Rxo_h + (long)p0 * N * Qs,
@@ -838,18 +836,13 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
     }
     for (int a0 = 0; a0 < v; a0 += pc) {
       const int na = std::min(pc, v - a0);
-      pole_transform_f64(h, N, Q, Qp, L, u, npole, o + a0, na, T);
+      pole_transform_blas(h, N, Q, Qp, L, u, npole, o + a0, na, T);
       if (F16) row_stats(T, per_pole, Qp, na, N, Q, 1, 0, eRv + a0, nrm + 1, st);
       split_rows<F16>(T, per_pole, Qp, na, N, perm, Rxv_h + (long)a0 * N * Qs,
                       Rxv_l + (long)a0 * N * Qs, (long)N * Qs, Qs, Qs,
                       F16 ? eRv + a0 : nullptr, 1, 0, st);
       // Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q] for this chunk of a
-      Gemm g;
-      g.M = o; g.N = Q; g.K = N; g.batch = na;
-      g.A = u; g.sAm = 1; g.sAk = npole;
-      g.B = T; g.sBb = per_pole; g.sBk = Qp; g.sBn = 1;
-      g.C = Tov; g.sCb = Qp; g.sCm = (long)na * Qp; g.sCn = 1;
-      gemm_f64_padded(g, Qp, st);
+      lov_transform_blas(h, N, Q, Qp, u, npole, o, na, T, per_pole, Tov);
       // rows (i, a); one exponent per row, stored at i * v + a
       if (F16) row_stats(Tov, (long)na * Qp, Qp, o, na, Q, v, 1, eOV + a0, nrm + 2, st);
       split_rows<F16>(Tov, (long)na * Qp, Qp, o, na, perm, Rov_h + (long)a0 * Qs,
