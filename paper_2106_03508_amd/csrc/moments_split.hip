@@ -38,7 +38,11 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int KS = 32;        // k depth of one MFMA step
 constexpr int KV = KS / 8;    // 16-byte vectors per row per step
-constexpr int KVP = KV + 1;   // padded LDS row (conflict-free fragment reads)
+// LDS rows hold KV 16-byte vectors with no padding; vector kv of row r sits
+// in slot kv ^ swz(r). A fragment read (16 consecutive rows, one vector each)
+// and a loader store (4 whole rows per 16 lanes) then hit distinct bank
+// groups within every group of 8 or 16 lanes.
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & (KV - 1); }
 constexpr int NT = 256;
 constexpr int KC_STEPS = 8;   // float32 accumulation chunk of the SYRK (8 x 32 columns)
 
@@ -178,9 +182,9 @@ constexpr int XNT = 512;
 
 template <bool F16>
 __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
-  // two stages (double buffer) x (hi, lo): 160 KiB, the whole LDS of a CU
-  __shared__ u16x8 sA[2][2][GT][KVP];
-  __shared__ u16x8 sB[2][2][GT][KVP];
+  // two stages (double buffer) x (hi, lo): 128 KiB
+  __shared__ u16x8 sA[2][2][GT][KV];
+  __shared__ u16x8 sB[2][2][GT][KV];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long G = (long)gridDim.x;
   long logical = xcd_remap(blockIdx.x, G);
@@ -214,11 +218,11 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
   auto store = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int r = (tid >> 2) + 128 * i;
-      sA[buf][0][r][kv] = pa[i];
-      sA[buf][1][r][kv] = pa[2 + i];
-      sB[buf][0][r][kv] = pb[i];
-      sB[buf][1][r][kv] = pb[2 + i];
+      const int r = (tid >> 2) + 128 * i, slot = kv ^ swz(r);
+      sA[buf][0][r][slot] = pa[i];
+      sA[buf][1][r][slot] = pa[2 + i];
+      sB[buf][0][r][slot] = pb[i];
+      sB[buf][1][r][slot] = pb[2 + i];
     }
   };
   const int fr = lane & 15, fk = lane >> 4;
@@ -241,12 +245,14 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
     u16x8 ah[8], al[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      ah[i] = sA[buf][0][wm + 16 * i + fr][fk];
-      al[i] = sA[buf][1][wm + 16 * i + fr][fk];
+      const int r = wm + 16 * i + fr;
+      ah[i] = sA[buf][0][r][fk ^ swz(r)];
+      al[i] = sA[buf][1][r][fk ^ swz(r)];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const u16x8 bh = sB[buf][0][wn + 16 * j + fr][fk], bl = sB[buf][1][wn + 16 * j + fr][fk];
+      const int r = wn + 16 * j + fr;
+      const u16x8 bh = sB[buf][0][r][fk ^ swz(r)], bl = sB[buf][1][r][fk ^ swz(r)];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         acc[i][j] = mfma<F16>(ah[i], bh, acc[i][j]);
@@ -382,8 +388,10 @@ constexpr int TS = 64;   // SYRK output tile
 
 template <bool F16>
 __global__ __launch_bounds__(NT, 2) void syrk_split_kernel(SyrkArgs a) {
-  __shared__ u16x8 sX[4][TS][KVP];   // Z hi, Z lo, wZ hi, wZ lo (x rows)
-  __shared__ u16x8 sY[2][TS][KVP];   // Z hi, Z lo (y rows)
+  // two stages (double buffer) of: Z hi, Z lo, wZ hi, wZ lo (x rows) and
+  // Z hi, Z lo (y rows); 48 KiB
+  __shared__ u16x8 sX[2][4][TS][KV];
+  __shared__ u16x8 sY[2][2][TS][KV];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // (split, tile) work items numbered split-major and dealt to XCDs in
   // contiguous ranges, so the tiles reading one K range share an L2
@@ -399,46 +407,69 @@ __global__ __launch_bounds__(NT, 2) void syrk_split_kernel(SyrkArgs a) {
   const int x0 = xt * TS, y0 = yt * TS;
   const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
 
-  u16x8 rx[4], ry[2];
-  auto load = [&](long kb) {
+  // Loader: thread tid moves vector (tid + NT i) of the x operands (4 arrays
+  // x 64 rows x KV vectors) and of the y operands (2 arrays); its global row
+  // pointers and LDS slots are fixed for the whole K range. Rows past N read
+  // row N - 1 instead (they only feed output rows or columns that are not
+  // stored), and a step's 32 columns never pass the row length (a multiple of
+  // 32), so every load is unconditional and in bounds; this keeps the
+  // compiler's count of loads in flight exact across the two register stages.
+  const u16* gx[4];
+  const u16* gy[2];
+  int lx[4], ly[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int idx = tid + NT * i;
-      const int arr = idx / (TS * KV), rr = (idx / KV) % TS, kv = idx % KV;
-      const int x = x0 + rr;
-      const long k = kb + 8 * kv;
-      const u16* base = arr == 0 ? a.Zh : arr == 1 ? a.Zl : arr == 2 ? a.Wh : a.Wl;
-      rx[i] = (x < a.N && k < k1) ? *reinterpret_cast<const u16x8*>(base + (long)x * a.ldz + k)
-                                  : zero8;
-      if (k < k1 && k + 8 > k1)   // vector straddles the end of the chunk
+  for (int i = 0; i < 4; ++i) {
+    const int idx = tid + NT * i;
+    const int arr = idx / (TS * KV), rr = (idx / KV) % TS, kv = idx % KV;
+    const u16* base = arr == 0 ? a.Zh : arr == 1 ? a.Zl : arr == 2 ? a.Wh : a.Wl;
+    gx[i] = base + (long)min(x0 + rr, a.N - 1) * a.ldz + 8 * kv;
+    lx[i] = (arr * TS + rr) * KV + (kv ^ swz(rr));
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int idx = tid + NT * i;
+    const int arr = idx / (TS * KV), rr = (idx / KV) % TS, kv = idx % KV;
+    const u16* base = arr == 0 ? a.Zh : a.Zl;
+    gy[i] = base + (long)min(y0 + rr, a.N - 1) * a.ldz + 8 * kv;
+    ly[i] = (arr * TS + rr) * KV + (kv ^ swz(rr));
+  }
+  // register stages: the global loads run two k steps ahead of the MFMAs.
+  // Every step issues its six loads with no branch (steps past the end
+  // re-read the last one, unused), so the wait before an LDS store covers
+  // only the older stage; columns >= k1 of the last step are zeroed at store
+  // time.
+  const long nsteps = (k1 - k0 + KS - 1) / KS;
+  const long kb_last = k0 + (nsteps - 1) * KS;
+  auto load = [&](long kb, u16x8 (&rx)[4], u16x8 (&ry)[2]) {
+    kb = min(kb, kb_last);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rx[i] = *reinterpret_cast<const u16x8*>(gx[i] + kb);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) ry[i] = *reinterpret_cast<const u16x8*>(gy[i] + kb);
+  };
+  auto store = [&](int buf, long kb, u16x8 (&rx)[4], u16x8 (&ry)[2]) {
+    if (kb + KS > k1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long k = kb + 8 * ((tid + NT * i) % KV);
+#pragma unroll
         for (int e = 0; e < 8; ++e)
           if (k + e >= k1) rx[i][e] = 0;
-    }
+      }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int idx = tid + NT * i;
-      const int arr = idx / (TS * KV), rr = (idx / KV) % TS, kv = idx % KV;
-      const int y = y0 + rr;
-      const long k = kb + 8 * kv;
-      const u16* base = arr == 0 ? a.Zh : a.Zl;
-      ry[i] = (y < a.N && k < k1) ? *reinterpret_cast<const u16x8*>(base + (long)y * a.ldz + k)
-                                  : zero8;
-      if (k < k1 && k + 8 > k1)
+      for (int i = 0; i < 2; ++i) {
+        const long k = kb + 8 * ((tid + NT * i) % KV);
+#pragma unroll
         for (int e = 0; e < 8; ++e)
           if (k + e >= k1) ry[i][e] = 0;
+      }
     }
-  };
-  auto store = [&]() {
+    u16x8* bx = &sX[buf][0][0][0];
+    u16x8* by = &sY[buf][0][0][0];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int idx = tid + NT * i;
-      sX[idx / (TS * KV)][(idx / KV) % TS][idx % KV] = rx[i];
-    }
+    for (int i = 0; i < 4; ++i) bx[lx[i]] = rx[i];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int idx = tid + NT * i;
-      sY[idx / (TS * KV)][(idx / KV) % TS][idx % KV] = ry[i];
-    }
+    for (int i = 0; i < 2; ++i) by[ly[i]] = ry[i];
   };
 
   const int fr = lane & 15, fk = lane >> 4;
@@ -472,22 +503,27 @@ __global__ __launch_bounds__(NT, 2) void syrk_split_kernel(SyrkArgs a) {
       }
   };
 
-  const long nsteps = (k1 - k0 + KS - 1) / KS;
-  load(k0);
-  for (long step = 0; step < nsteps; ++step) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (step + 1 < nsteps) load(k0 + (step + 1) * KS);
+  // Step s reads LDS stage s & 1. Its body first reloads the register stage
+  // that held step s (already in LDS) with step s + 2, then runs the MFMAs,
+  // then writes step s + 1 (loaded during step s - 1) into the other LDS
+  // stage, whose last readers (step s - 1) the previous barrier has passed.
+  // Steps run in pairs with no branch around loads or stores; for odd nsteps
+  // the last body multiplies the zeroed data of step nsteps (all its columns
+  // are >= k1), which adds exact zeros.
+  auto body = [&](long step, int buf, u16x8 (&cx)[4], u16x8 (&cy)[2], u16x8 (&nx)[4],
+                  u16x8 (&ny)[2]) {
+    load(k0 + (step + 2) * KS, cx, cy);
     u16x8 xh[2], xl[2], wh[2], wl[2], yh[2], yl[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      xh[i] = sX[0][wm + 16 * i + fr][fk];
-      xl[i] = sX[1][wm + 16 * i + fr][fk];
-      wh[i] = sX[2][wm + 16 * i + fr][fk];
-      wl[i] = sX[3][wm + 16 * i + fr][fk];
-      yh[i] = sY[0][wn + 16 * i + fr][fk];
-      yl[i] = sY[1][wn + 16 * i + fr][fk];
+      const int rx_ = wm + 16 * i + fr, ry_ = wn + 16 * i + fr;
+      const int sx = fk ^ swz(rx_), sy = fk ^ swz(ry_);
+      xh[i] = sX[buf][0][rx_][sx];
+      xl[i] = sX[buf][1][rx_][sx];
+      wh[i] = sX[buf][2][rx_][sx];
+      wl[i] = sX[buf][3][rx_][sx];
+      yh[i] = sY[buf][0][ry_][sy];
+      yl[i] = sY[buf][1][ry_][sy];
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -503,6 +539,17 @@ __global__ __launch_bounds__(NT, 2) void syrk_split_kernel(SyrkArgs a) {
         v1[i][j] = mfma<F16>(wl[i], yl[j], v1[i][j]);
       }
     if ((step + 1) % KC_STEPS == 0) flush();
+    store(buf ^ 1, k0 + (step + 1) * KS, nx, ny);
+    __syncthreads();
+  };
+  u16x8 ax[4], ay[2], bx[4], by[2];
+  load(k0, ax, ay);
+  load(k0 + KS, bx, by);
+  store(0, k0, ax, ay);
+  __syncthreads();
+  for (long step = 0; step < nsteps; step += 2) {
+    body(step, 0, ax, ay, bx, by);
+    body(step + 1, 1, bx, by, ax, ay);
   }
   flush();
 
