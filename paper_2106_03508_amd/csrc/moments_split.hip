@@ -194,25 +194,31 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
   logical -= b.start[k];
   const int tm = (int)(logical / a.tiles_n), tn = (int)(logical % a.tiles_n);
   const int m0 = tm * GT, n0 = tn * GT;
-  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-  // loader: per operand 256 rows x 4 vectors; thread -> rows tid/4 + 128 i, vector tid % 4
+  // loader: per operand 256 rows x 4 vectors; thread -> rows tid/4 + 128 i,
+  // vector tid % 4. Rows past M (N) read row M - 1 (N - 1): they only feed
+  // output rows (columns) that are not stored. The loads carry no condition,
+  // so the operand base pointers stay in registers across the K loop.
   const int kv = tid & 3;
+  const u16* const Ah = a.Ah;
+  const u16* const Al = a.Al;
+  const u16* const Bh = a.Bh;
+  const u16* const Bl = a.Bl;
   long oa[2], ob[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int r = (tid >> 2) + 128 * i;
-    const int m = m0 + r, n = n0 + r;
-    oa[i] = m < a.M ? (long)(m / a.mA) * a.sAp + (long)(m % a.mA) * a.sAx + 8 * kv : -1;
-    ob[i] = n < a.Nn ? (long)(n / a.nB) * a.sBq + (long)(n % a.nB) * a.sBc + 8 * kv : -1;
+    const int m = min(m0 + r, a.M - 1), n = min(n0 + r, a.Nn - 1);
+    oa[i] = (long)(m / a.mA) * a.sAp + (long)(m % a.mA) * a.sAx + 8 * kv;
+    ob[i] = (long)(n / a.nB) * a.sBq + (long)(n % a.nB) * a.sBc + 8 * kv;
   }
   u16x8 pa[4], pb[4];
   auto load = [&](int kb) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      pa[i] = oa[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Ah + oa[i] + kb) : zero8;
-      pa[2 + i] = oa[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Al + oa[i] + kb) : zero8;
-      pb[i] = ob[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Bh + ob[i] + kb) : zero8;
-      pb[2 + i] = ob[i] >= 0 ? *reinterpret_cast<const u16x8*>(a.Bl + ob[i] + kb) : zero8;
+      pa[i] = *reinterpret_cast<const u16x8*>(Ah + oa[i] + kb);
+      pa[2 + i] = *reinterpret_cast<const u16x8*>(Al + oa[i] + kb);
+      pb[i] = *reinterpret_cast<const u16x8*>(Bh + ob[i] + kb);
+      pb[2 + i] = *reinterpret_cast<const u16x8*>(Bl + ob[i] + kb);
     }
   };
   auto store = [&](int buf) {
@@ -235,34 +241,44 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
   const int nsteps = a.Qs / KS;
   // stage k lives in buffer k & 1: the next stage's global loads are issued
   // before this stage's MFMAs and written to the other buffer after them, so
-  // one barrier per stage separates every write from the reads of that buffer
+  // one barrier per stage separates every write from the reads of that buffer.
+  // The last stage re-loads itself and writes the idle buffer, so the loop
+  // body has no branch around its loads and stores.
   load(0);
   store(0);
   __syncthreads();
   for (int step = 0; step < nsteps; ++step) {
     const int buf = step & 1;
-    if (step + 1 < nsteps) load((step + 1) * KS);
-    u16x8 ah[8], al[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int r = wm + 16 * i + fr;
-      ah[i] = sA[buf][0][r][fk ^ swz(r)];
-      al[i] = sA[buf][1][r][fk ^ swz(r)];
-    }
+    load(min(step + 1, nsteps - 1) * KS);
+    // keep the loads ahead of the MFMAs (the scheduler would otherwise sink
+    // them next to their LDS stores and expose their latency)
+    __builtin_amdgcn_sched_barrier(0);
+    // B fragments of the wave's four column blocks stay in registers while
+    // the eight row blocks stream through one A fragment pair at a time
+    u16x8 bh[4], bl[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = wn + 16 * j + fr;
-      const u16x8 bh = sB[buf][0][r][fk ^ swz(r)], bl = sB[buf][1][r][fk ^ swz(r)];
+      bh[j] = sB[buf][0][r][fk ^ swz(r)];
+      bl[j] = sB[buf][1][r][fk ^ swz(r)];
+    }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        acc[i][j] = mfma<F16>(ah[i], bh, acc[i][j]);
-        acc[i][j] = mfma<F16>(ah[i], bl, acc[i][j]);
-        acc[i][j] = mfma<F16>(al[i], bh, acc[i][j]);
+    for (int i = 0; i < 8; ++i) {
+      const int r = wm + 16 * i + fr;
+      const u16x8 ah = sA[buf][0][r][fk ^ swz(r)], al = sA[buf][1][r][fk ^ swz(r)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = mfma<F16>(ah, bh[j], acc[i][j]);
+        acc[i][j] = mfma<F16>(ah, bl[j], acc[i][j]);
+        acc[i][j] = mfma<F16>(al, bh[j], acc[i][j]);
       }
     }
-    if (step + 1 < nsteps) store(buf ^ 1);
+    store(buf ^ 1);
     __syncthreads();
   }
+  float* const C = a.C;
+  const long ldc = a.ldc;
+  const int M = a.M, Nn = a.Nn;
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -271,7 +287,7 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + crow(lane, r);
         const int n = n0 + wn + 16 * j + fr;
-        if (m < a.M && n < a.Nn) a.C[(long)m * a.ldc + n] = acc[i][j][r];
+        if (m < M && n < Nn) C[(long)m * ldc + n] = acc[i][j][r];
       }
 }
 
