@@ -330,13 +330,20 @@ __device__ __forceinline__ void pair_values(float x1, float x2, bool diag, float
   split<F16>(wscale * (wgt * zm), out[6], out[7]);
 }
 
-// Grid: (element blocks, pairs); one workgroup row per pole pair. With V = 2
-// a thread takes two adjacent inner poles c, c+1 (nc even: the slab reads are
-// 8-byte and the Z stores 4-byte aligned, since pair column offsets are
-// multiples of nc and Z rows are multiples of 32 long).
+// Grid: one workgroup per (element block, pair), numbered block-major with
+// the pairs inner and dealt to XCDs in contiguous ranges, so the workgroups
+// writing neighbouring pairs' columns of one Z row (which share cache lines)
+// run on one XCD at about the same time. A thread takes PU elements (all
+// slab loads first, then the arithmetic and stores); with V = 2 an element
+// is two adjacent inner poles c, c+1 (nc even: the slab reads are 8-byte and
+// the Z stores 4-byte aligned, since pair column offsets are multiples of nc
+// and Z rows are multiples of 32 long).
+constexpr int PU = 4;
+
 template <bool F16, int V>
 __global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
-  const int pr = blockIdx.y;
+  const long logical = xcd_remap(blockIdx.x, (long)gridDim.x);
+  const int xb = (int)(logical / a.npairs), pr = (int)(logical % a.npairs);
   const int p = a.pa[pr], q = a.pb[pr];
   const bool diag = (p == q);
   const long colbase = a.pcol[pr] - a.col_base;
@@ -347,34 +354,58 @@ __global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
                         ? a.X1 + (long)(q - a.P0) * a.N * a.ld1 + (long)(p - a.P1) * a.nc
                         : a.X2 + (long)(q - a.P1) * a.N * a.ld2 + (long)(p - a.P0) * a.nc;
   const long ld2 = (a.P0 == a.P1) ? a.ld1 : a.ld2;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < per; e += gridDim.x * 256) {
+  // per inner pole c of this pair: the two fp16 scale exponents and the
+  // weight, gathered once per workgroup (the exponent tables can be strided
+  // in c) instead of once per element
+  extern __shared__ int ptab[];
+  int* t1 = ptab;
+  int* t2 = ptab + a.nc;
+  float* tw = reinterpret_cast<float*>(ptab + 2 * a.nc);
+  for (int cc = threadIdx.x; cc < a.nc; cc += 256) {
+    if constexpr (F16) {
+      t1[cc] = a.eR[p] + a.eS[(long)q * a.sEp + (long)cc * a.sEc] - 2 * EMAX;
+      t2[cc] = diag ? 0 : a.eR[q] + a.eS[(long)p * a.sEp + (long)cc * a.sEc] - 2 * EMAX;
+    }
+    tw[cc] = (float)(a.ep[p] + a.ep[q] - a.ec[cc]);
+  }
+  const int e0 = xb * (256 * PU) + threadIdx.x;
+  float x1[PU][V], x2[PU][V];
+#pragma unroll
+  for (int u = 0; u < PU; ++u) {
+    const int e = e0 + 256 * u;
+#pragma unroll
+    for (int t = 0; t < V; ++t) x1[u][t] = x2[u][t] = 0.f;
+    if (e >= per) continue;
     const int x = e / ncv, c = V * (e - x * ncv);
-    const long o = (long)x * a.ldz + colbase + c;
-    float x1[V], x2[V];
     if constexpr (V == 2) {
       const float2 v1 = *reinterpret_cast<const float2*>(r1 + (long)x * a.ld1 + c);
-      x1[0] = v1.x; x1[1] = v1.y;
+      x1[u][0] = v1.x; x1[u][1] = v1.y;
       if (!diag) {
         const float2 v2 = *reinterpret_cast<const float2*>(r2 + (long)x * ld2 + c);
-        x2[0] = v2.x; x2[1] = v2.y;
-      } else {
-        x2[0] = x2[1] = 0.f;
+        x2[u][0] = v2.x; x2[u][1] = v2.y;
       }
     } else {
-      x1[0] = r1[(long)x * a.ld1 + c];
-      x2[0] = diag ? 0.f : r2[(long)x * ld2 + c];
+      x1[u][0] = r1[(long)x * a.ld1 + c];
+      if (!diag) x2[u][0] = r2[(long)x * ld2 + c];
     }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PU; ++u) {
+    const int e = e0 + 256 * u;
+    if (e >= per) continue;
+    const int x = e / ncv, c = V * (e - x * ncv);
+    const long o = (long)x * a.ldz + colbase + c;
     u16 v[V][8];
 #pragma unroll
     for (int t = 0; t < V; ++t) {
       const int cc = c + t;
+      float y1 = x1[u][t], y2 = x2[u][t];
       if constexpr (F16) {
-        x1[t] = ldexpf(x1[t], a.eR[p] + a.eS[(long)q * a.sEp + (long)cc * a.sEc] - 2 * EMAX);
-        if (!diag)
-          x2[t] = ldexpf(x2[t], a.eR[q] + a.eS[(long)p * a.sEp + (long)cc * a.sEc] - 2 * EMAX);
+        y1 = ldexpf(y1, t1[cc]);
+        if (!diag) y2 = ldexpf(y2, t2[cc]);
       }
-      const float wgt = (float)(a.ep[p] + a.ep[q] - a.ec[cc]);
-      pair_values<F16>(x1[t], x2[t], diag, wgt, a.zscale, a.wscale, v[t]);
+      pair_values<F16>(y1, y2, diag, tw[cc], a.zscale, a.wscale, v[t]);
     }
     u16* dst[4] = {a.Zh, a.Zl, a.Wh, a.Wl};
 #pragma unroll
@@ -802,11 +833,14 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
         ProfScope ps(h, "moments.pair", 0.0, 4.0 * 2.0 * tot + 8.0 * N * (double)Kc);
         const bool two = (nc % 2 == 0) && (kcap % 2 == 0);
         const long per = (long)N * nc / (two ? 2 : 1);
-        AGF2_REQUIRE((long)N * nc < (1L << 31) - 256 && pa.npairs <= 65535,
+        const long nxb = (per + 256L * PU - 1) / (256L * PU);
+        AGF2_REQUIRE((long)N * nc < (1L << 31) - 256 * PU && nxb * pa.npairs < (1L << 31),
                      "pair chunk too large");
-        const dim3 grid((unsigned)std::min<long>((per + 255) / 256, 16384), (unsigned)pa.npairs);
-        if (two) hipLaunchKernelGGL((pair_split_kernel<F16, 2>), grid, dim3(256), 0, st, pa);
-        else hipLaunchKernelGGL((pair_split_kernel<F16, 1>), grid, dim3(256), 0, st, pa);
+        const dim3 grid((unsigned)(nxb * pa.npairs));
+        const size_t tab = 3 * sizeof(int) * (size_t)nc;   // per-c table (LDS)
+        AGF2_REQUIRE(tab <= 64 * 1024, "pair chunk: inner pole count too large");
+        if (two) hipLaunchKernelGGL((pair_split_kernel<F16, 2>), grid, dim3(256), tab, st, pa);
+        else hipLaunchKernelGGL((pair_split_kernel<F16, 1>), grid, dim3(256), tab, st, pa);
         AGF2_CHECK_LAUNCH();
       }
       int nsplit = choose_splits(Kc, nlower, nsplit_max,
