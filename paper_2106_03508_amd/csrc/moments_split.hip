@@ -262,8 +262,7 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
       bh[j] = sB[buf][0][r][fk ^ swz(r)];
       bl[j] = sB[buf][1][r][fk ^ swz(r)];
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    auto rows = [&](int i) {
       const int r = wm + 16 * i + fr;
       const u16x8 ah = sA[buf][0][r][fk ^ swz(r)], al = sA[buf][1][r][fk ^ swz(r)];
 #pragma unroll
@@ -272,8 +271,17 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
         acc[i][j] = mfma<F16>(ah, bl[j], acc[i][j]);
         acc[i][j] = mfma<F16>(al, bh[j], acc[i][j]);
       }
-    }
+    };
+    // the next stage goes to LDS halfway through the MFMAs (its loads have
+    // had half a step to land), so the barrier that ends the step does not
+    // also wait for the stores
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rows(i);
+    __builtin_amdgcn_sched_barrier(0);
     store(buf ^ 1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 4; i < 8; ++i) rows(i);
     __syncthreads();
   }
   float* const C = a.C;
