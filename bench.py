@@ -197,10 +197,12 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, prec, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings),
-    or None when there is none or the kernel's source has changed since."""
+    or None when there is none, when it was taken at another precision or on
+    another workload (another kernel or launch shape), or when the kernel's
+    source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -208,7 +210,7 @@ def measured_traffic(kernel):
     with open(path) as f:
         t = json.load(f)
     rec = t.get(kernel)
-    if rec is None:
+    if rec is None or rec.get("precision") != prec or rec.get("workload") != workload:
         return None
     src = os.path.join(ROOT, rec["source"])
     with open(src, "rb") as f:
@@ -354,7 +356,7 @@ def main():
         "traffic_note": None,
         "cpu_baseline": None,
     }
-    tr = measured_traffic(dom)
+    tr = measured_traffic(dom, args.prec, args.workload)
     if tr is not None:
         out["roofline"]["traffic"] = tr["bytes_per_launch"]
         out["traffic_note"] = (f"HBM bytes per launch of {dom} (FETCH_SIZE + WRITE_SIZE, scaled "
