@@ -440,8 +440,28 @@ def fit_shift(F, e_aux, v_aux, nelec, shift0=0.0, bracket=2.0, tol=1e-10,
     return shift, n_eig
 
 
+def shift_derivative(lam, u, n):
+    """First-order response of the occupied physical density to the common
+    auxiliary shift Delta, at a fixed number n of occupied poles.
+
+    Reading: the extended Hamiltonian depends on Delta through Delta times
+    the projector A = 1 - P onto the auxiliary space, so first-order
+    perturbation theory of its eigenvectors gives, with c_l = u[:, l] the
+    physical part of eigenvector l and P_ij = c_i . c_j (i occupied, j
+    virtual), M_ij = P_ij / (lam_j - lam_i):
+        dD/dDelta = 2 (C_o M C_v^T + C_v M^T C_o^T),
+        dN/dDelta = tr(dD/dDelta) = 4 sum_ij M_ij P_ij  (> 0).
+    Rotations among the occupied poles leave D unchanged and drop out.
+    Returns (dN, dD)."""
+    Co, Cv = u[:, :n], u[:, n:]
+    P = Co.T @ Cv
+    M = P / (lam[None, n:] - lam[:n, None])
+    G = Co @ M @ Cv.T
+    return 4.0 * np.sum(M * P), 2.0 * (G + G.T)
+
+
 def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
-              max_cycle=50, bracket=2.0, shift0=0.0, diis_space=6):
+              max_cycle=50, bracket=2.0, shift0=0.0, diis_space=6, newton_max=1e-3):
     """Density relaxation with the chemical potential held at the right
     electron number (relaxation passage after the self-consistency
     discussion), on the compressed extended Hamiltonian.
@@ -451,6 +471,12 @@ def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
     stop when the norm (Frobenius) of the change of D is below tol_rdm1, else
     the next F is
     F[D], DIIS-extrapolated with the fixed-point residual F[D] - F as error.
+    Reading (how Delta is fitted while the density still moves): when the
+    count at the current Delta misses the cycle's tolerance by a Newton step
+    |g / (dN/dDelta)| <= newton_max, Delta takes that step and D is taken to
+    first order in it (shift_derivative) instead of refitting; otherwise, and
+    always for the returned density, Delta is fitted to tolerance and D comes
+    from the eigendecomposition at the fitted Delta.
     Reading: the tolerance bounds the whole change of the density matrix, so
     the energy it leaves unconverged does not grow with the basis size.
     The returned F is the one diagonalised last, so the returned poles are
@@ -468,18 +494,32 @@ def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
         # settled; earlier cycles, whose density is still moving, to
         # 0.01 x its last change (at most 1e-6)
         tol_c = max(tol_nelec, min(1e-6, 1e-2 * err_prev))
-        shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift,
-                              bracket=bracket, tol=tol_c)
-        n_eig += ne
         lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
         n_eig += 1
-        uo = u[:, :n]
-        D_new = 2.0 * uo @ uo.T
+        g0 = cnt - nelec
+        first_order = False
+        if abs(g0) >= tol_c:
+            dN, dD = shift_derivative(lam, u, n)
+            step = -g0 / dN if dN > 0 else np.inf
+            if abs(step) <= newton_max:
+                uo = u[:, :n]
+                D_new = 2.0 * uo @ uo.T + step * dD
+                shift += step
+                first_order = True
+            else:
+                shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift,
+                                      bracket=bracket, tol=tol_c)
+                n_eig += ne
+                lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
+                n_eig += 1
+        if not first_order:
+            uo = u[:, :n]
+            D_new = 2.0 * uo @ uo.T
         err = np.linalg.norm(D_new - D)
         err_prev = err
         D = D_new
         if err < tol_rdm1:
-            if tol_c > tol_nelec:
+            if first_order or tol_c > tol_nelec:
                 # the returned density meets tol_nelec (same F)
                 shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift,
                                       bracket=bracket, tol=tol_nelec)

@@ -192,6 +192,26 @@ __global__ void sqdiff_kernel(long n, const double* a, const double* b, double* 
     out[i] = a[i] - b[i];
 }
 
+// M[i][j] = P[i][j] / (lam[no + j] - lam[i]) over the occupied x virtual poles
+__global__ void newton_weights_kernel(long n, int nv, int no, const double* P,
+                                      const double* lam, double* M) {
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n;
+       k += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(k / nv), j = (int)(k % nv);
+    M[k] = P[k] / (lam[no + j] - lam[i]);
+  }
+}
+
+// D[x][y] += a (G[x][y] + G[y][x])
+__global__ void add_sym_kernel(int N, double a, const double* G, double* D) {
+  const long nn = (long)N * N;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < nn;
+       k += (long)gridDim.x * blockDim.x) {
+    const int x = (int)(k / N), y = (int)(k % N);
+    D[k] += a * (G[k] + G[(long)y * N + x]);
+  }
+}
+
 __global__ void add_scalar_kernel(long n, double d, double* x) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
        i += (long)gridDim.x * blockDim.x)
@@ -373,6 +393,67 @@ struct FockLoop {
     return aufbau(n, hlam, hw, nelec);
   }
 
+  // the last eigendecomposition no longer belongs to the contents of F
+  void invalidate() { solved_F = nullptr; solved_shift = NAN; }
+
+  // First-order response to the common auxiliary shift at the last
+  // eigendecomposition, with no occupied poles (eigenvectors l = rows of the
+  // row-major view of H, physical part = first N columns):
+  //   P = C_o^T C_v, M_ij = P_ij / (lam_j - lam_i),
+  //   dN/dDelta = 4 sum M.P, dD/dDelta = 2 (G + G^T) with G = C_o M C_v^T.
+  // If the Newton step -g0 / dN is at most max_step, adds step x dD/dDelta to
+  // D (the exact density at the last solve) and returns the step; otherwise
+  // returns NAN and leaves D alone.
+  // Newton step -g0 / (dN/dDelta) at the last eigendecomposition (NAN when
+  // the derivative is not positive); leaves M in the workspace.
+  double newton_step(int no, double g0) {
+    const int nv = n - no;
+    if (no <= 0 || nv <= 0) return NAN;
+    hipStream_t st = h.stream;
+    const long ov = (long)no * nv;
+    double* P = h.ws_fock[1].as<double>(2 * ov + (long)N * nv + (long)N * N);
+    double* M = P + ov;
+    Gemm g;
+    g.M = no; g.N = nv; g.K = N;
+    g.A = H; g.sAm = n; g.sAk = 1;
+    g.B = H + (long)no * n; g.sBk = 1; g.sBn = n;
+    g.C = P; g.sCm = nv; g.sCn = 1;
+    gemm_f64(g, st);
+    hipLaunchKernelGGL(newton_weights_kernel, dim3(nblk(ov)), dim3(256), 0, st, ov, nv, no, P,
+                       lam, M);
+    AGF2_CHECK_LAUNCH();
+    const double dN = 4.0 * dot_f64(h, ov, M, P);
+    return dN > 0.0 ? -g0 / dN : NAN;
+  }
+
+  double first_order(int no, double g0, double max_step, double* D) {
+    const double step = newton_step(no, g0);
+    if (!(std::fabs(step) <= max_step)) return NAN;
+    hipStream_t st = h.stream;
+    const int nv = n - no;
+    const long ov = (long)no * nv;
+    double* P = h.ws_fock[1].as<double>(2 * ov + (long)N * nv + (long)N * N);
+    double* M = P + ov;
+    double* T = M + ov;
+    double* G = T + (long)N * nv;
+    Gemm t;
+    t.M = N; t.N = nv; t.K = no;
+    t.A = H; t.sAm = 1; t.sAk = n;
+    t.B = M; t.sBk = nv; t.sBn = 1;
+    t.C = T; t.sCm = nv; t.sCn = 1;
+    gemm_f64(t, st);
+    Gemm u;
+    u.M = N; u.N = N; u.K = nv;
+    u.A = T; u.sAm = nv; u.sAk = 1;
+    u.B = H + (long)no * n; u.sBk = n; u.sBn = 1;
+    u.C = G; u.sCm = N; u.sCn = 1;
+    gemm_f64(u, st);
+    hipLaunchKernelGGL(add_sym_kernel, dim3(nblk((long)N * N)), dim3(256), 0, st, N,
+                       2.0 * step, G, D);
+    AGF2_CHECK_LAUNCH();
+    return step;
+  }
+
   double count_n(int nocc) const {
     double c = 0.0;
     for (int l = 0; l < nocc; ++l) c += 2.0 * hw[l];
@@ -383,10 +464,26 @@ struct FockLoop {
   // bracket by doubling steps, then Illinois regula falsi (count is
   // non-decreasing in the shift for a fixed number of occupied poles).
   double fit_shift(const double* F, double shift0, const agf2_fock_opts& o, double tol) {
-    Aufbau a = solve(F, shift0);
+    Aufbau a = (solved_shift == shift0 && solved_F == F) ? aufbau(n, hlam, hw, nelec)
+                                                         : solve(F, shift0);
     double shift = shift0;
     int nocc = a.n;
     double cnt = a.count;
+    // Newton steps with the analytic derivative while each at least halves
+    // the error at an unchanged occupied count (one eigensolve per step)
+    for (int it = 0; it < 8; ++it) {
+      const double g0 = cnt - nelec;
+      if (std::fabs(g0) < tol) return shift;
+      const double step = newton_step(nocc, g0);
+      if (!(std::fabs(step) <= o.bracket)) break;
+      const Aufbau an = solve(F, shift + step);
+      const double g1 = count_n(nocc) - nelec;
+      if (!(std::fabs(g1) <= 0.5 * std::fabs(g0))) break;   // (solve kept; bracketing re-solves)
+      last_change = std::fabs(step);
+      shift += step;
+      if (an.n != nocc) { nocc = an.n; cnt = an.count; continue; }
+      cnt = an.count;
+    }
     for (int rep = 0; rep < 8; ++rep) {
       const double g0 = cnt - nelec;
       if (std::fabs(g0) < tol) return shift;
@@ -439,6 +536,9 @@ struct FockLoop {
     return shift;
   }
 };
+
+// largest shift step the Fock loop takes to first order instead of refitting
+constexpr double kNewtonMax = 1e-3;
 
 // tiny dense solve (partial pivoting) for DIIS
 bool solve_small(int n, std::vector<double> A, std::vector<double>& b) {
@@ -542,11 +642,8 @@ FockLoopResult fock_loop_impl(Handle& h, int nphys, int naux, const double* Lpq,
     // settled; earlier cycles, whose density is still moving, to 0.01 x its
     // last change (at most 1e-6)
     const double tol_c = std::max(o.tol_nelec, std::min(1e-6, 1e-2 * err_prev));
-    // fit the shift at F to tolerance tol, then D = 2 sum_{l < n*} phi_l phi_l^T
-    // (physical block) into Dn
-    auto fit_and_density = [&](double tol) {
-      d = fl.fit_shift(F, d, o, tol);
-      if (!(fl.solved_shift == d && fl.solved_F == F)) fl.solve(F, d);
+    // D = 2 sum_{l < n*} phi_l phi_l^T (physical block) of the last solve into Dn
+    auto density = [&]() {
       a = aufbau(fl.n, fl.hlam, fl.hw, (double)nelec);
       Gemm g;
       g.M = N; g.N = N; g.K = a.n;
@@ -556,15 +653,44 @@ FockLoopResult fock_loop_impl(Handle& h, int nphys, int naux, const double* Lpq,
       if (a.n > 0) gemm_f64(g, s);
       else AGF2_HIP(hipMemsetAsync(Dn, 0, nn * sizeof(double), s));
     };
-    fit_and_density(tol_c);
+    // fit the shift at F to tolerance tol, then the density at the fitted shift
+    auto fit_and_density = [&](double tol) {
+      d = fl.fit_shift(F, d, o, tol);
+      if (!(fl.solved_shift == d && fl.solved_F == F)) fl.solve(F, d);
+      density();
+    };
+    // Solve at the current shift. If the count misses tol_c by a Newton step
+    // of at most kNewtonMax, take that step and the density to first order in
+    // it (no further eigensolve); otherwise fit the shift to tol_c.
+    bool first_order = false;
+    {
+      const Aufbau a0 = (fl.solved_shift == d && fl.solved_F == F)
+                            ? aufbau(fl.n, fl.hlam, fl.hw, (double)nelec)
+                            : fl.solve(F, d);
+      const double g0 = a0.count - (double)nelec;
+      if (std::fabs(g0) < tol_c) {
+        density();
+      } else {
+        density();
+        const double step = fl.first_order(a0.n, g0, kNewtonMax, Dn);
+        if (std::isfinite(step)) {
+          d += step;
+          fl.last_change = std::fabs(step);
+          first_order = true;
+        } else {
+          fit_and_density(tol_c);
+        }
+      }
+    }
     // Frobenius norm of the change of D
     hipLaunchKernelGGL(sqdiff_kernel, dim3(nblk(nn)), dim3(256), 0, s, nn, Dn, rdm1, Fn);
     AGF2_CHECK_LAUNCH();
     const double err = std::sqrt(dot_f64(h, nn, Fn, Fn));
     err_prev = err;
     if (err < o.tol_rdm1) {
-      // converged: the returned density meets tol_nelec (same F, so no new J/K)
-      if (tol_c > o.tol_nelec) fit_and_density(o.tol_nelec);
+      // converged: the returned density is exact and meets tol_nelec (same F,
+      // so no new J/K)
+      if (first_order || tol_c > o.tol_nelec) fit_and_density(o.tol_nelec);
       AGF2_HIP(hipMemcpyAsync(rdm1, Dn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
       converged = true;
       break;
@@ -576,6 +702,7 @@ FockLoopResult fock_loop_impl(Handle& h, int nphys, int naux, const double* Lpq,
     AGF2_CHECK_LAUNCH();
     diis.update(Fn, Dn);
     AGF2_HIP(hipMemcpyAsync(F, Fn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    fl.invalidate();
   }
   if (cycle > o.max_cycle) cycle = o.max_cycle;
   AGF2_HIP(hipMemcpyAsync(fock, F, nn * sizeof(double), hipMemcpyDeviceToDevice, s));

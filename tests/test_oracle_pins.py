@@ -293,6 +293,48 @@ def test_electron_count_monotone_in_shift():
     assert np.all(np.diff(cs) >= -1e-12)
 
 
+def test_shift_derivative_matches_finite_differences():
+    """The first-order response of the density and of the electron count to
+    the auxiliary shift, against central differences of the exact
+    eigendecomposition at a fixed number of occupied poles."""
+    eps, L, nocc, h, (eo, vo, ev, vv), fl = _iteration0()
+    e_aux = np.concatenate([eo, ev]); v_aux = np.hstack([vo, vv])
+    F, d0 = fl["fock"], fl["shift"] + 0.013
+    lam, u, n, cnt, mu = O._solve(F, e_aux, v_aux, d0, 2 * nocc)
+    dN, dD = O.shift_derivative(lam, u, n)
+
+    def dens(d):
+        _, ud, *_ = O._solve(F, e_aux, v_aux, d, 2 * nocc)
+        return 2.0 * ud[:, :n] @ ud[:, :n].T
+
+    step = 1e-5
+    fd = (dens(d0 + step) - dens(d0 - step)) / (2 * step)
+    assert np.abs(dD - fd).max() < 1e-7 * max(1.0, np.abs(fd).max())
+    assert abs(dN - np.trace(fd)) < 1e-7 * max(1.0, abs(dN))
+    assert dN > 0
+    assert np.abs(dD - dD.T).max() == 0.0
+    # one Newton step brings the count to second order in the step
+    g0 = cnt - 2 * nocc
+    s1 = -g0 / dN
+    c1 = np.trace(dens(d0 + s1))
+    assert abs(c1 - 2 * nocc) < 1e-2 * abs(g0)
+
+
+def test_fock_loop_first_order_steps_keep_the_solution():
+    """The first-order shift steps change the path, not the converged loop:
+    the same result with them switched off (every cycle refitted)."""
+    eps, L, nocc, h, (eo, vo, ev, vv), fl = _iteration0()
+    e_aux = np.concatenate([eo, ev]); v_aux = np.hstack([vo, vv])
+    ref = O.fock_loop(h, L, 2 * nocc, e_aux, v_aux, O.reference_density(eps.shape[0], nocc),
+                      newton_max=0.0)
+    assert fl["converged"] and ref["converged"]
+    assert fl["nocc_pole"] == ref["nocc_pole"]
+    assert abs(fl["shift"] - ref["shift"]) < 1e-8
+    assert np.abs(fl["rdm1"] - ref["rdm1"]).max() < 1e-8
+    assert np.abs(fl["e_pole"] - ref["e_pole"]).max() < 1e-8
+    assert fl["n_eig"] < ref["n_eig"]
+
+
 def test_energy_two_sided_equals_direct_form():
     """For poles that are exact eigenpairs of the extended Hamiltonian, the
     virtual-pole/lesser form of the GM two-body term equals the direct
