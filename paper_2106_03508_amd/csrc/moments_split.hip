@@ -431,6 +431,14 @@ __global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
   }
 }
 
+// out[a][i] = in[i][a] (o x v ints)
+__global__ void transpose_int_kernel(int o, int v, const int* in, int* out) {
+  const long n = (long)o * v;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n;
+       k += (long)gridDim.x * blockDim.x)
+    out[k] = in[(k % o) * v + k / o];
+}
+
 struct SyrkArgs {
   const u16* Zh; const u16* Zl; const u16* Wh; const u16* Wl; long ldz;
   int N; long K; long kper;
@@ -460,7 +468,6 @@ __global__ __launch_bounds__(NT, 2) void syrk_split_kernel(SyrkArgs a) {
   const long k0 = (long)s * a.kper, k1 = std::min(a.K, k0 + a.kper);
   if (k1 <= k0) return;
   const int x0 = xt * TS, y0 = yt * TS;
-  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
 
   // Loader: thread tid moves vector (tid + NT i) of the x operands (4 arrays
   // x 64 rows x KV vectors) and of the y operands (2 arrays); its global row
@@ -890,10 +897,11 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
   u16 *Rov_h = Sov, *Rov_l = Sov + (long)o * v * Qs;
   // fp16 scale exponents: per occupied pole, per virtual pole, per (i, a) row;
   // then the squared-norm maxima of the three tensors' Q rows
-  int* ex = h.ws_misc[7].as<int>((long)npole + (long)o * v + 8);
+  int* ex = h.ws_misc[7].as<int>((long)npole + 2L * o * v + 8);
   int* eRo = ex;
   int* eRv = ex + o;
   int* eOV = ex + npole;
+  int* eVO = eOV + (long)o * v;   // the same exponents as [a][i] (greater part: inner i contiguous)
   unsigned long long* nrm = reinterpret_cast<unsigned long long*>(
       h.ws_red.as<double>(4096) + 4000);   // 3 slots
   if (F16) {
@@ -957,6 +965,11 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
   }
   PartScales lesser, greater;
   if (F16) {
+    if ((long)o * v > 0) {
+      hipLaunchKernelGGL(transpose_int_kernel, dim3((unsigned)std::min<long>(((long)o * v + 255) / 256, 4096)),
+                         dim3(256), 0, st, o, v, eOV, eVO);
+      AGF2_CHECK_LAUNCH();
+    }
     // Cauchy-Schwarz: |(xp|qc)| <= |R[p][x]| |S[q][c]| (Q-space norms), so
     // |Z|, |wZ| <= sqrt(6) * max|R| max|S| (* max|w|)
     unsigned long long hn[3];
@@ -969,9 +982,9 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
     double eo_max = 0.0, ev_max = 0.0;
     for (int i = 0; i < o; ++i) eo_max = std::max(eo_max, std::fabs(he[i]));
     for (int a = o; a < npole; ++a) ev_max = std::max(ev_max, std::fabs(he[a]));
-    auto make = [&](const int* eR, double nR2, double wmax, long sEp, long sEc) {
+    auto make = [&](const int* eR, const int* eS, double nR2, double wmax, long sEp, long sEc) {
       PartScales sc;
-      sc.eR = eR; sc.eS = eOV; sc.sEp = sEp; sc.sEc = sEc;
+      sc.eR = eR; sc.eS = eS; sc.sEp = sEp; sc.sEc = sEc;
       const double zb = std::sqrt(6.0 * nR2 * n2[2]);
       const double wb = zb * wmax;
       const int fZ = EMAX - exponent_above(zb), fW = EMAX - exponent_above(wb);
@@ -981,8 +994,8 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
       sc.u1scale = std::ldexp(1.0, -fZ - fW);
       return sc;
     };
-    lesser = make(eRo, n2[0], 2.0 * eo_max + ev_max, (long)v, 1L);
-    greater = make(eRv, n2[1], 2.0 * ev_max + eo_max, 1L, (long)v);
+    lesser = make(eRo, eOV, n2[0], 2.0 * eo_max + ev_max, (long)v, 1L);
+    greater = make(eRv, eVO, n2[1], 2.0 * ev_max + eo_max, (long)o, 1L);
   }
   moments_part_split<F16>(h, N, Q, Qs, Rxo_h, Rxo_l, (long)N * Qs, Qs, Rov_h, Rov_l,
                           (long)v * Qs, Qs, e, o, e + o, v, lesser, m0o, m1o);
