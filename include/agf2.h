@@ -163,7 +163,13 @@ void agf2_fock_opts_default(agf2_fock_opts* opts);
  * the aufbau count 2 * sum_{l<n} |u_l|^2 equals nelec, diagonalises
  *   [[F, v_se], [v_se^T, diag(e_se + Delta)]],
  * rebuilds rdm1 = 2 sum_{l<n} u_l u_l^T and F = F[rdm1] (DIIS on F), until
- * the Frobenius norm of the change of rdm1 is below tol_rdm1.
+ * the Frobenius norm of the change of rdm1 is below tol_rdm1. The fit takes
+ * Newton steps with the analytic derivative of the count (first-order
+ * perturbation of the eigenvectors in Delta) before bracketing; while the
+ * density still moves, a cycle whose count misses its tolerance by a Newton
+ * step of at most 1e-3 Ha takes that step and the density to first order in
+ * it instead of refitting. The returned density is always from an exact
+ * fit to tol_nelec.
  *   hcore      device [nphys][nphys]; Lpq device [naux][nphys][nphys]
  *   nelec      electrons (even, 0 < nelec < 2 * (nphys + naux_se))
  *   naux_se    auxiliaries; v_se device [nphys][naux_se] (row stride
