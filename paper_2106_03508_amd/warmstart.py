@@ -12,7 +12,7 @@ rate) and moves tensors.
 Evaluation: every held-out system is converged twice by agf2_run, from the
 cold start and with the predicted correction as dm_init; the report gives
 the iterations of both, their wall time and the differences of the converged
-IP, EA and total energy (the cold-start result is the judge).
+IP, EA and total energy (the cold-start result is the reference).
 
     python -m paper_2106_03508_amd.warmstart train --out params.npy
     python -m paper_2106_03508_amd.warmstart eval --params params.npy
