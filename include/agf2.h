@@ -152,7 +152,7 @@ typedef struct {
 } agf2_fock_opts;
 
 /* Fill opts with the defaults: tol_rdm1 1e-8, tol_nelec 1e-10, bracket 2,
- * step0 0.01, max_cycle 50, diis_space 6. */
+ * step0 0.01, max_cycle 50, diis_space 8. */
 void agf2_fock_opts_default(agf2_fock_opts* opts);
 
 /*

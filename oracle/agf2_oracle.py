@@ -461,7 +461,7 @@ def shift_derivative(lam, u, n):
 
 
 def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
-              max_cycle=50, bracket=2.0, shift0=0.0, diis_space=6, newton_max=1e-3):
+              max_cycle=50, bracket=2.0, shift0=0.0, diis_space=8, newton_max=1e-3):
     """Density relaxation with the chemical potential held at the right
     electron number (relaxation passage after the self-consistency
     discussion), on the compressed extended Hamiltonian.

@@ -801,7 +801,7 @@ void agf2_fock_opts_default(agf2_fock_opts* o) {
   o->bracket = 2.0;
   o->step0 = 0.01;
   o->max_cycle = 50;
-  o->diis_space = 6;
+  o->diis_space = 8;
 }
 
 agf2_status agf2_create(agf2_handle_t* out, int device, void* stream) {
