@@ -339,7 +339,21 @@ void blas_check(rocblas_status bs, const char* what) {
 
 }  // namespace
 
-int slab_f64_tc(int nc) { return nc >= 48 ? 64 : (nc >= 24 ? 32 : 16); }
+// Inner tile width for nc inner poles: the width whose padded tiles cost least,
+// a tile of width TC counted as TC + 16 columns (its fixed per-tile work,
+// mainly the 64 x-rows of both R operands); ties go to the wider tile.
+int slab_f64_tc(int nc) {
+  int best = 64;
+  long best_cost = -1;
+  for (int tc : {64, 32, 16}) {
+    const long cost = (long)((nc + tc - 1) / tc) * (tc + 16);
+    if (best_cost < 0 || cost < best_cost) {
+      best = tc;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
 
 long slab_f64_tiles(const SlabF64& a) { return (long)a.npairs * a.tiles_x * a.tiles_c; }
 
