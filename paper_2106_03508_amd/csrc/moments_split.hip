@@ -39,10 +39,13 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int KS = 32;        // k depth of one MFMA step
 constexpr int KV = KS / 8;    // 16-byte vectors per row per step
 // LDS rows hold KV 16-byte vectors with no padding; vector kv of row r sits
-// in slot kv ^ swz(r). A fragment read (16 consecutive rows, one vector each)
-// and a loader store (4 whole rows per 16 lanes) then hit distinct bank
-// groups within every group of 8 or 16 lanes.
-__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & (KV - 1); }
+// in slot kv ^ ((r >> 1) & 3). Of the layouts timed on gfx950 (plain rows,
+// rows padded to five vectors, and several XOR and rotation schemes) this is
+// the one whose fragment reads (16 consecutive rows, one vector each) run at
+// the speed of contiguous 16-byte reads; its loader stores (4 whole rows per
+// 16 lanes) do too. The padded rows and the other schemes take ~1.55x longer
+// per fragment read.
+__device__ __forceinline__ int swz(int r) { return (r >> 1) & (KV - 1); }
 constexpr int NT = 256;
 constexpr int KC_STEPS = 8;   // float32 accumulation chunk of the SYRK (8 x 32 columns)
 
