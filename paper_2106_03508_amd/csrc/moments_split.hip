@@ -936,9 +936,12 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
     ProfScope ps(h, "moments.transform",
                  2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
                  8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
-    // float64 staging in chunks of poles (<= ~4 GiB each)
+    // float64 staging in chunks of poles (<= ~4 GiB each), a multiple of 64
+    // poles where possible (the library GEMMs are cut into 64-pole calls)
     const long per_pole = (long)N * Qp;
-    const int pc = (int)std::max<long>(1, std::min<long>(npole, (1L << 29) / per_pole));
+    long pcl = std::max<long>(1, std::min<long>(npole, (1L << 29) / per_pole));
+    if (pcl > 64 && pcl < npole) pcl = pcl / 64 * 64;
+    const int pc = (int)pcl;
     double* T = h.ws_moments[3].as<double>((long)pc * per_pole + (long)o * pc * Qp);
     double* Tov = T + (long)pc * per_pole;
     for (int p0 = 0; p0 < o; p0 += pc) {
