@@ -499,8 +499,11 @@ def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
         g0 = cnt - nelec
         first_order = False
         if abs(g0) >= tol_c:
-            dN, dD = shift_derivative(lam, u, n)
-            step = -g0 / dN if dN > 0 else np.inf
+            with np.errstate(divide="ignore", invalid="ignore"):
+                dN, dD = shift_derivative(lam, u, n)
+            # no step when the derivative is not finite and positive (an
+            # occupied and a virtual pole at the same energy)
+            step = -g0 / dN if (np.isfinite(dN) and dN > 0) else np.inf
             if abs(step) <= newton_max:
                 uo = u[:, :n]
                 D_new = 2.0 * uo @ uo.T + step * dD

@@ -423,7 +423,9 @@ struct FockLoop {
                        lam, M);
     AGF2_CHECK_LAUNCH();
     const double dN = 4.0 * dot_f64(h, ov, M, P);
-    return dN > 0.0 ? -g0 / dN : NAN;
+    // an occupied and a virtual pole at the same energy make M infinite:
+    // no step then (the caller falls back to the bracketing fit)
+    return (dN > 0.0 && std::isfinite(dN)) ? -g0 / dN : NAN;
   }
 
   double first_order(int no, double g0, double max_step, double* D) {
