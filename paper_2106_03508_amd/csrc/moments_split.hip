@@ -345,13 +345,13 @@ __device__ __forceinline__ void pair_values(float x1, float x2, bool diag, float
 // the pairs inner and dealt to XCDs in contiguous ranges, so the workgroups
 // writing neighbouring pairs' columns of one Z row (which share cache lines)
 // run on one XCD at about the same time. A thread takes PU elements (all
-// slab loads first, then the arithmetic and stores); with V = 2 an element
+// slab loads first, then the arithmetic and stores; PU = 8 for long inner
+// pole ranges, where the per-pair table fill is amortised over fewer rows,
+// else 4); with V = 2 an element
 // is two adjacent inner poles c, c+1 (nc even: the slab reads are 8-byte and
 // the Z stores 4-byte aligned, since pair column offsets are multiples of nc
 // and Z rows are multiples of 32 long).
-constexpr int PU = 4;
-
-template <bool F16, int V>
+template <bool F16, int V, int PU>
 __global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
   const long logical = xcd_remap(blockIdx.x, (long)gridDim.x);
   const int xb = (int)(logical / a.npairs), pr = (int)(logical % a.npairs);
@@ -851,14 +851,20 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
         ProfScope ps(h, "moments.pair", 0.0, 4.0 * 2.0 * tot + 8.0 * N * (double)Kc);
         const bool two = (nc % 2 == 0) && (kcap % 2 == 0);
         const long per = (long)N * nc / (two ? 2 : 1);
-        const long nxb = (per + 256L * PU - 1) / (256L * PU);
-        AGF2_REQUIRE((long)N * nc < (1L << 31) - 256 * PU && nxb * pa.npairs < (1L << 31),
+        const int pu = nc >= 256 ? 8 : 4;
+        const long nxb = (per + 256L * pu - 1) / (256L * pu);
+        AGF2_REQUIRE((long)N * nc < (1L << 31) - 256 * pu && nxb * pa.npairs < (1L << 31),
                      "pair chunk too large");
         const dim3 grid((unsigned)(nxb * pa.npairs));
         const size_t tab = 3 * sizeof(int) * (size_t)nc;   // per-c table (LDS)
         AGF2_REQUIRE(tab <= 64 * 1024, "pair chunk: inner pole count too large");
-        if (two) hipLaunchKernelGGL((pair_split_kernel<F16, 2>), grid, dim3(256), tab, st, pa);
-        else hipLaunchKernelGGL((pair_split_kernel<F16, 1>), grid, dim3(256), tab, st, pa);
+        if (pu == 8) {
+          if (two) hipLaunchKernelGGL((pair_split_kernel<F16, 2, 8>), grid, dim3(256), tab, st, pa);
+          else hipLaunchKernelGGL((pair_split_kernel<F16, 1, 8>), grid, dim3(256), tab, st, pa);
+        } else {
+          if (two) hipLaunchKernelGGL((pair_split_kernel<F16, 2, 4>), grid, dim3(256), tab, st, pa);
+          else hipLaunchKernelGGL((pair_split_kernel<F16, 1, 4>), grid, dim3(256), tab, st, pa);
+        }
         AGF2_CHECK_LAUNCH();
       }
       int nsplit = choose_splits(Kc, nlower, nsplit_max,
