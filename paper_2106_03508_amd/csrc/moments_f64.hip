@@ -60,24 +60,26 @@ __device__ void slab_tile(const SlabF64& a, long logical, double (*A1)[BK][LD],
   const double* Sq = a.S + (long)q * a.sSp;
   const double* Sp = a.S + (long)p * a.sSp;
 
-  // loader: thread -> k = tid % 16, rows tid/16 + 16 i
+  // loader: thread -> k = tid % 16, rows tid/16 + 16 i. Rows past N and
+  // columns past nc read the last row / column instead (their outputs are
+  // not stored), so the loads carry no condition and run ahead of the MFMAs.
   const int lk = tid & 15, lr = tid >> 4;
+  long orow[4], ocol[CB];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) orow[i] = (long)min(x0 + lr + 16 * i, a.N - 1) * a.sRx + lk;
+#pragma unroll
+  for (int i = 0; i < CB; ++i) ocol[i] = (long)min(c0 + lr + 16 * i, a.nc - 1) * a.sSc + lk;
   double r1[4], r2[4], s1[CB], s2[CB];
   auto load = [&](int kb) {
-    const int k = kb + lk;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int x = x0 + lr + 16 * i;
-      const bool xin = x < a.N;
-      r1[i] = xin ? Rp[(long)x * a.sRx + k] : 0.0;
-      r2[i] = (xin && !diag) ? Rq[(long)x * a.sRx + k] : 0.0;
+      r1[i] = Rp[orow[i] + kb];
+      r2[i] = Rq[orow[i] + kb];
     }
 #pragma unroll
     for (int i = 0; i < CB; ++i) {
-      const int c = c0 + lr + 16 * i;
-      const bool cin = c < a.nc;
-      s1[i] = cin ? Sq[(long)c * a.sSc + k] : 0.0;
-      s2[i] = (cin && !diag) ? Sp[(long)c * a.sSc + k] : 0.0;
+      s1[i] = Sq[ocol[i] + kb];
+      s2[i] = Sp[ocol[i] + kb];
     }
   };
   auto store = [&](int buf) {
@@ -106,9 +108,12 @@ __device__ void slab_tile(const SlabF64& a, long logical, double (*A1)[BK][LD],
   load(0);
   store(0);
   __syncthreads();
+  // The mirrored product runs for diagonal pairs too (its inputs are then the
+  // same rows and its result is not used), so the MFMA loop has no branch.
   for (int step = 0; step < nsteps; ++step) {
     const int buf = step & 1;
-    if (step + 1 < nsteps) load((step + 1) * BK);
+    load(min(step + 1, nsteps - 1) * BK);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const double x1 = A1[buf][kk + fk][wr + fr];
@@ -117,12 +122,11 @@ __device__ void slab_tile(const SlabF64& a, long logical, double (*A1)[BK][LD],
       for (int j = 0; j < CB; ++j) {
         c1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, B1[buf][kk + fk][16 * j + fr], c1[j],
                                                      0, 0, 0);
-        if (!diag)
-          c2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, B2[buf][kk + fk][16 * j + fr],
-                                                       c2[j], 0, 0, 0);
+        c2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, B2[buf][kk + fk][16 * j + fr], c2[j],
+                                                     0, 0, 0);
       }
     }
-    if (step + 1 < nsteps) store(buf ^ 1);
+    store(buf ^ 1);
     __syncthreads();
   }
 
