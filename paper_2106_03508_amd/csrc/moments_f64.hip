@@ -188,6 +188,11 @@ __global__ __launch_bounds__(NT) void slab_f64_grouped(const SlabF64* jobs, cons
 }
 
 // One SYRK tile: lower-triangle tile t, K split s.
+// UNCOND: the loads of a K step carry no condition and run ahead of the
+// MFMAs (the grouped kernel, whose items each span few K steps, gains from
+// it); otherwise the loads are predicated and the last step skips the
+// prefetch (faster for the one-item-per-workgroup kernel, measured).
+template <bool UNCOND>
 __device__ void syrk_tile(const SyrkF64& a, int t, int s, double (*X)[BK][LD],
                           double (*Y)[BK][LD], double (*W)[BK]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -197,18 +202,39 @@ __device__ void syrk_tile(const SyrkF64& a, int t, int s, double (*X)[BK][LD],
   const int yt = t - xt * (xt + 1) / 2;
   const long k0 = (long)s * a.kper, k1 = std::min(a.K, k0 + a.kper);
   const int x0 = xt * TB, y0 = yt * TB;
+  // loader: thread -> k = tid % 16, rows tid/16 + 16 i. Rows past N read row
+  // N - 1 (their outputs are not stored); a column past the split's end is
+  // read at the split's last column and replaced by zero, so the loads carry
+  // no condition and run ahead of the MFMAs.
   const int lk = tid & 15, lr = tid >> 4;
+  long ox[4], oy[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ox[i] = (long)min(x0 + lr + 16 * i, a.N - 1) * a.ldz;
+    oy[i] = (long)min(y0 + lr + 16 * i, a.N - 1) * a.ldz;
+  }
   double rx[4], ry[4], rw = 0.0;
   auto load = [&](long kb) {
     const long k = kb + lk;
     const bool kin = k < k1;
+    if constexpr (UNCOND) {
+      const long kc = kin ? k : k1 - 1;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int x = x0 + lr + 16 * i, y = y0 + lr + 16 * i;
-      rx[i] = (kin && x < a.N) ? a.Z[(long)x * a.ldz + k] : 0.0;
-      ry[i] = (kin && y < a.N) ? a.Z[(long)y * a.ldz + k] : 0.0;
+      for (int i = 0; i < 4; ++i) {
+        const double vx = a.Z[ox[i] + kc], vy = a.Z[oy[i] + kc];
+        rx[i] = kin ? vx : 0.0;
+        ry[i] = kin ? vy : 0.0;
+      }
+      const double vw = a.w[kc];
+      rw = kin ? vw : 0.0;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        rx[i] = kin ? a.Z[ox[i] + k] : 0.0;
+        ry[i] = kin ? a.Z[oy[i] + k] : 0.0;
+      }
+      if (tid < BK) rw = kin ? a.w[k] : 0.0;
     }
-    if (tid < BK) rw = kin ? a.w[k] : 0.0;
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -236,7 +262,12 @@ __device__ void syrk_tile(const SyrkF64& a, int t, int s, double (*X)[BK][LD],
   __syncthreads();
   for (long step = 0; step < nsteps; ++step) {
     const int buf = step & 1;
-    if (step + 1 < nsteps) load(k0 + (step + 1) * BK);
+    if constexpr (UNCOND) {
+      load(k0 + min(step + 1, nsteps - 1) * BK);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (step + 1 < nsteps) {
+      load(k0 + (step + 1) * BK);
+    }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const double wk = W[buf][kk + fk];
@@ -256,7 +287,8 @@ __device__ void syrk_tile(const SyrkF64& a, int t, int s, double (*X)[BK][LD],
           u1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xw[i], yb[j], u1[i][j], 0, 0, 0);
         }
     }
-    if (step + 1 < nsteps) store(buf ^ 1);
+    // (UNCOND: the last step writes the idle buffer)
+    if (UNCOND || step + 1 < nsteps) store(buf ^ 1);
     __syncthreads();
   }
   double* P0 = a.part + (long)s * a.part_stride;
@@ -280,7 +312,7 @@ __global__ __launch_bounds__(NT) void syrk_f64_kernel(SyrkF64 a) {
   __shared__ double X[2][BK][LD], Y[2][BK][LD], W[2][BK];
   // split-major items dealt to XCDs in contiguous ranges (one K range per L2)
   const long item = xcd_remap(blockIdx.x, (long)a.tiles * a.nsplit);
-  syrk_tile(a, (int)(item % a.tiles), (int)(item / a.tiles), X, Y, W);
+  syrk_tile<false>(a, (int)(item % a.tiles), (int)(item / a.tiles), X, Y, W);
 }
 
 __global__ __launch_bounds__(NT) void syrk_f64_grouped(const SyrkF64* jobs, const long* prefix,
@@ -290,7 +322,7 @@ __global__ __launch_bounds__(NT) void syrk_f64_grouped(const SyrkF64* jobs, cons
     const int j = find_job(prefix, njobs, it);
     const SyrkF64& a = jobs[j];
     const long l = it - prefix[j];
-    syrk_tile(a, (int)(l % a.tiles), (int)(l / a.tiles), X, Y, W);
+    syrk_tile<true>(a, (int)(l % a.tiles), (int)(l / a.tiles), X, Y, W);
   }
 }
 
