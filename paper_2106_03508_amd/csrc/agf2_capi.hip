@@ -396,16 +396,12 @@ struct FockLoop {
   // the last eigendecomposition no longer belongs to the contents of F
   void invalidate() { solved_F = nullptr; solved_shift = NAN; }
 
-  // First-order response to the common auxiliary shift at the last
-  // eigendecomposition, with no occupied poles (eigenvectors l = rows of the
-  // row-major view of H, physical part = first N columns):
-  //   P = C_o^T C_v, M_ij = P_ij / (lam_j - lam_i),
-  //   dN/dDelta = 4 sum M.P, dD/dDelta = 2 (G + G^T) with G = C_o M C_v^T.
-  // If the Newton step -g0 / dN is at most max_step, adds step x dD/dDelta to
-  // D (the exact density at the last solve) and returns the step; otherwise
-  // returns NAN and leaves D alone.
-  // Newton step -g0 / (dN/dDelta) at the last eigendecomposition (NAN when
-  // the derivative is not positive); leaves M in the workspace.
+  // Newton step -g0 / (dN/dDelta) at the last eigendecomposition, from the
+  // first-order response to the common auxiliary shift (eigenvectors l = rows
+  // of the row-major view of H, physical part = first N columns):
+  //   P = C_o^T C_v, M_ij = P_ij / (lam_j - lam_i), dN/dDelta = 4 sum M.P.
+  // NAN when the derivative is not positive and finite; leaves P and M in the
+  // workspace.
   double newton_step(int no, double g0) {
     const int nv = n - no;
     if (no <= 0 || nv <= 0) return NAN;
@@ -428,6 +424,10 @@ struct FockLoop {
     return (dN > 0.0 && std::isfinite(dN)) ? -g0 / dN : NAN;
   }
 
+  // If the Newton step is at most max_step, adds step x dD/dDelta to D (the
+  // exact density at the last solve), with dD/dDelta = 2 (G + G^T) and
+  // G = C_o M C_v^T, and returns the step; otherwise returns NAN and leaves D
+  // alone.
   double first_order(int no, double g0, double max_step, double* D) {
     const double step = newton_step(no, g0);
     if (!(std::fabs(step) <= max_step)) return NAN;
@@ -483,7 +483,7 @@ struct FockLoop {
       if (!(std::fabs(g1) <= 0.5 * std::fabs(g0))) break;   // (solve kept; bracketing re-solves)
       last_change = std::fabs(step);
       shift += step;
-      if (an.n != nocc) { nocc = an.n; cnt = an.count; continue; }
+      nocc = an.n;
       cnt = an.count;
     }
     for (int rep = 0; rep < 8; ++rep) {

@@ -94,6 +94,25 @@ def test_fock_build(h, alpha):
     assert rel(got, ref) < 1e-12
 
 
+# one exchange tile; ragged tiles; many column splits; two chunks of slices
+# (L above 1 GiB, the second chunk ragged) with 64- and with 128-wide tiles
+@pytest.mark.parametrize("nmo,naux", [(24, 80), (130, 100), (200, 700), (520, 500),
+                                      (1000, 140)])
+def test_fock_build_shapes(h, nmo, naux):
+    from paper_2106_03508_amd import agf2
+    L = syn.df_tensor(7, nmo, naux, max(nmo // 5, 1))
+    rng = np.random.default_rng(nmo)
+    A = rng.standard_normal((nmo, nmo + 7)) / np.sqrt(nmo)
+    D = A @ A.T
+    hc = np.diag(syn.orbital_energies(7, nmo, max(nmo // 5, 1)))
+    J, K = O.coulomb_exchange(L, D)
+    ref = hc + J - 0.5 * K
+    got = host(agf2.agf2_fock_build(h, dev(L), dev(hc), dev(D), 1.0))
+    print(nmo, naux, f"{rel(got, ref):.2e}", flush=True)
+    assert rel(got, ref) < 1e-12
+    assert np.array_equal(got, got.T)
+
+
 def _moments(seed=2, nmo=40, naux=60, npole=100, nocc=35):
     L = syn.df_tensor(seed, nmo, naux, 5)
     e, u = syn.random_poles(seed, nmo, npole, nocc)
