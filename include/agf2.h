@@ -113,7 +113,10 @@ agf2_status agf2_build_moments(agf2_handle_t handle, agf2_precision prec,
  * hcore = diag(eps) gives the one-electron Hamiltonian that makes a
  * determinant self-consistent with orbital energies eps).
  *   Lpq   device [naux][nphys][nphys]; hcore, rdm1 device [nphys][nphys]
+ *         (every Lpq[Q] and rdm1 symmetric: the products read them in
+ *         either orientation; the output is then exactly symmetric).
  *   fock  device [nphys][nphys] output (may not alias the inputs).
+ * Errors: AGF2_ERR_ARG for bad sizes, NULL pointers or nphys > 46340.
  */
 agf2_status agf2_fock_build(agf2_handle_t handle, int nphys, int naux,
                             const double* Lpq, const double* hcore,

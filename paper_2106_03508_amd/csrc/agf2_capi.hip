@@ -906,6 +906,7 @@ agf2_status agf2_fock_build(agf2_handle_t hh, int nphys, int naux, const double*
                             double* fock) {
   return guarded(hh, [&](Handle& h) {
     AGF2_REQUIRE(nphys >= 1 && naux >= 1, "nphys and naux must be >= 1");
+    AGF2_REQUIRE(nphys <= 46340, "nphys must be <= 46340");
     AGF2_REQUIRE(Lpq && hcore && rdm1 && fock, "NULL array argument");
     AGF2_REQUIRE(fock != hcore && fock != rdm1, "fock may not alias an input");
     fock_build(h, nphys, naux, Lpq, hcore, rdm1, alpha, fock);

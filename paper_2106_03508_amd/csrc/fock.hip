@@ -13,14 +13,14 @@ namespace {
 
 constexpr int RT = 256;
 
-// rho[Q] = sum_rs L[Q][r][s] D[r][s]   (one workgroup per Q)
-__global__ __launch_bounds__(RT) void rho_kernel(const double* L, const double* D,
-                                                 int N, double* rho) {
+// rho[Q] = sum_rs L[Q][r][s] D[r][s] = tr(D L_Q), read off the diagonal of
+// slice Q of X = D [L_Q ...]   (one workgroup per Q)
+__global__ __launch_bounds__(RT) void rho_kernel(const double* X, int N, double* rho) {
   __shared__ double red[RT];
   const long nn = (long)N * N;
-  const double* LQ = L + blockIdx.x * nn;
+  const double* XQ = X + blockIdx.x * nn;
   double acc = 0.0;
-  for (long i = threadIdx.x; i < nn; i += RT) acc += LQ[i] * D[i];
+  for (int i = threadIdx.x; i < N; i += RT) acc += XQ[(long)i * (N + 1)];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int s = RT / 2; s > 0; s >>= 1) {
@@ -269,10 +269,10 @@ int exchange_splits(int N, int tiles, int kfull) {
 }
 
 // K's lower triangle += sum_Q L_Q (L_Q D)^T for the chunks of slices, X the
-// (L_Q D) of one chunk; partial slots zeroed here.
+// (L_Q D) of one chunk; partial slots zeroed here. Also rho[Q] = tr(L_Q D).
 template <int WB>
 void exchange_lower(Handle& h, int N, int Q, int QC, const double* L, const double* D,
-                    double* X, double* K) {
+                    double* X, double* K, double* rho) {
   hipStream_t st = h.stream;
   const long nn = (long)N * N;
   const int ts = 32 * WB, tiles_side = (N + ts - 1) / ts;
@@ -289,6 +289,8 @@ void exchange_lower(Handle& h, int N, int Q, int QC, const double* L, const doub
                       D, N, L + (long)q0 * nn, N, &zero, X, N);
     if (bs != rocblas_status_success)
       throw Error{AGF2_ERR_HIP, std::string("rocblas_dgemm: ") + rocblas_status_to_string(bs)};
+    hipLaunchKernelGGL(rho_kernel, dim3(qn), dim3(RT), 0, st, X, N, rho + q0);
+    AGF2_CHECK_LAUNCH();
     ExchLower a;
     a.L = L + (long)q0 * nn;
     a.Y = X;
@@ -311,11 +313,9 @@ void fock_build(Handle& h, int N, int Q, const double* L, const double* hcore,
                 const double* D, double alpha, double* F) {
   hipStream_t st = h.stream;
   const long nn = (long)N * N;
-  ProfScope ps(h, "fock.jk", 3.0 * Q * (double)nn * N + 4.0 * Q * (double)nn,
+  ProfScope ps(h, "fock.jk", 3.0 * Q * (double)nn * N + 2.0 * Q * (double)nn,
                8.0 * (3.0 * Q * nn + 3.0 * nn));
   double* rho = h.ws_fock[0].as<double>(Q);
-  hipLaunchKernelGGL(rho_kernel, dim3(Q), dim3(RT), 0, st, L, D, N, rho);
-  AGF2_CHECK_LAUNCH();
   // exchange K = sum_Q L_Q D L_Q, Q processed in chunks of qn slices:
   //   X = D [L_Q ...], one rocBLAS GEMM of N x (qn N) x N (column-major view:
   //       the memory of L_Q and D reads as L_Q and D, both symmetric); slice Q
@@ -338,9 +338,9 @@ void fock_build(Handle& h, int N, int Q, const double* L, const double* hcore,
     return t * (t + 1) / 2 * ts * ts;
   };
   if (padded(128) <= 1.08 * padded(64))
-    exchange_lower<4>(h, N, Q, QC, L, D, X, K);
+    exchange_lower<4>(h, N, Q, QC, L, D, X, K, rho);
   else
-    exchange_lower<2>(h, N, Q, QC, L, D, X, K);
+    exchange_lower<2>(h, N, Q, QC, L, D, X, K, rho);
   hipLaunchKernelGGL(fock_combine_kernel, dim3(nblocks(nn)), dim3(256), 0, st, L, rho,
                      Q, N, hcore, K, alpha, F);
   AGF2_CHECK_LAUNCH();
