@@ -7,7 +7,6 @@
 #include "agf2_internal.h"
 
 namespace agf2 {
-void gemm_f64_padded(const Gemm& g, int Npad, hipStream_t stream);
 
 namespace {
 
