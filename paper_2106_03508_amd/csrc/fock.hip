@@ -331,7 +331,8 @@ void fock_build(Handle& h, int N, int Q, const double* L, const double* hcore,
   double* X = h.ws_fock[1].as<double>((long)QC * nn);
   double* K = h.ws_fock[3].as<double>(nn);
   // 128-wide tiles (four MFMA blocks a side per wave) when their padded lower
-  // triangle is within 8% of the 64-wide tiles' (N >= ~768), else 64-wide
+  // triangle is within 8% of the 64-wide tiles' (e.g. N = 705-768, 833-896,
+  // 961-1024), else 64-wide
   auto padded = [N](long ts) {
     const long t = (N + ts - 1) / ts;
     return t * (t + 1) / 2 * ts * ts;

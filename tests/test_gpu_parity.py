@@ -94,17 +94,21 @@ def test_fock_build(h, alpha):
     assert rel(got, ref) < 1e-12
 
 
-# one exchange tile; ragged tiles; many column splits; two chunks of slices
-# (L above 1 GiB, the second chunk ragged) with 64- and with 128-wide tiles
-@pytest.mark.parametrize("nmo,naux", [(24, 80), (130, 100), (200, 700), (520, 500),
-                                      (1000, 140)])
+# one orbital; one exchange tile, full and one row past it; ragged tiles; many
+# column splits; both sides of each switch between 64- and 128-wide tiles
+# (128-wide for nmo 705-768, 64-wide for 704 and 769-832); two chunks of
+# slices (L above 1 GiB, the second chunk ragged) with 64- and with 128-wide
+# tiles
+@pytest.mark.parametrize("nmo,naux", [(1, 3), (24, 80), (64, 5), (65, 4), (130, 100),
+                                      (200, 700), (704, 20), (705, 20), (769, 20),
+                                      (520, 500), (1000, 140)])
 def test_fock_build_shapes(h, nmo, naux):
     from paper_2106_03508_amd import agf2
     L = syn.df_tensor(7, nmo, naux, max(nmo // 5, 1))
     rng = np.random.default_rng(nmo)
     A = rng.standard_normal((nmo, nmo + 7)) / np.sqrt(nmo)
     D = A @ A.T
-    hc = np.diag(syn.orbital_energies(7, nmo, max(nmo // 5, 1)))
+    hc = np.diag(np.linspace(-1.0, 2.0, nmo))
     J, K = O.coulomb_exchange(L, D)
     ref = hc + J - 0.5 * K
     got = host(agf2.agf2_fock_build(h, dev(L), dev(hc), dev(D), 1.0))
