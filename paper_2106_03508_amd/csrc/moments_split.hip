@@ -185,10 +185,13 @@ constexpr int XNT = 512;
 
 template <bool F16>
 __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
-  // two stages (double buffer) x (hi, lo): 128 KiB
-  __shared__ u16x8 sA[2][2][GT][KV];
-  __shared__ u16x8 sB[2][2][GT][KV];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // two stages, each its own LDS arrays (hi, lo planes of A and of B): 128 KiB.
+  // Separate arrays let the compiler see that the stage being read is not the
+  // one the direct loads are filling, so it waits for those loads only where
+  // the code says so (before the barrier that ends a step).
+  __shared__ u16x8 sA0[2][GT][KV], sB0[2][GT][KV], sA1[2][GT][KV], sB1[2][GT][KV];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const long G = (long)gridDim.x;
   long logical = xcd_remap(blockIdx.x, G);
   int k = 0;
@@ -197,41 +200,36 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
   logical -= b.start[k];
   const int tm = (int)(logical / a.tiles_n), tn = (int)(logical % a.tiles_n);
   const int m0 = tm * GT, n0 = tn * GT;
-  // loader: per operand 256 rows x 4 vectors; thread -> rows tid/4 + 128 i,
-  // vector tid % 4. Rows past M (N) read row M - 1 (N - 1): they only feed
-  // output rows (columns) that are not stored. The loads carry no condition,
-  // so the operand base pointers stay in registers across the K loop.
-  const int kv = tid & 3;
-  const u16* const Ah = a.Ah;
-  const u16* const Al = a.Al;
-  const u16* const Bh = a.Bh;
-  const u16* const Bl = a.Bl;
-  long oa[2], ob[2];
+  // direct-to-LDS loader: a stage is 64 blocks of 16 rows (block bl: plane
+  // bl / 16 of Ah, Al, Bh, Bl; rows 16 (bl % 16) ..); wave w fills blocks
+  // 8w .. 8w + 7. Lane l lands in LDS slot l % 4 of row l / 4 of its block,
+  // so it loads global vector (l % 4) ^ swz(row) of that row (the
+  // conflict-free layout of the fragment reads). Rows past M (N) read row
+  // M - 1 (N - 1): they only feed outputs that are not stored.
+  const u16* src[8];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int r = (tid >> 2) + 128 * i;
-    const int m = min(m0 + r, a.M - 1), n = min(n0 + r, a.Nn - 1);
-    oa[i] = (long)(m / a.mA) * a.sAp + (long)(m % a.mA) * a.sAx + 8 * kv;
-    ob[i] = (long)(n / a.nB) * a.sBq + (long)(n % a.nB) * a.sBc + 8 * kv;
-  }
-  u16x8 pa[4], pb[4];
-  auto load = [&](int kb) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      pa[i] = *reinterpret_cast<const u16x8*>(Ah + oa[i] + kb);
-      pa[2 + i] = *reinterpret_cast<const u16x8*>(Al + oa[i] + kb);
-      pb[i] = *reinterpret_cast<const u16x8*>(Bh + ob[i] + kb);
-      pb[2 + i] = *reinterpret_cast<const u16x8*>(Bl + ob[i] + kb);
+  for (int j = 0; j < 8; ++j) {
+    const int bl = 8 * wave + j, plane = bl >> 4;
+    const int r = 16 * (bl & 15) + (lane >> 2);
+    const int kvg = (lane & 3) ^ swz(r);
+    if (plane < 2) {
+      const int m = min(m0 + r, a.M - 1);
+      src[j] = (plane == 0 ? a.Ah : a.Al) + (long)(m / a.mA) * a.sAp +
+               (long)(m % a.mA) * a.sAx + 8 * kvg;
+    } else {
+      const int n = min(n0 + r, a.Nn - 1);
+      src[j] = (plane == 2 ? a.Bh : a.Bl) + (long)(n / a.nB) * a.sBq +
+               (long)(n % a.nB) * a.sBc + 8 * kvg;
     }
-  };
-  auto store = [&](int buf) {
+  }
+  typedef u16x8 Stage[2][GT][KV];
+  auto issue = [&](int kb, Stage& dA, Stage& dB) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int r = (tid >> 2) + 128 * i, slot = kv ^ swz(r);
-      sA[buf][0][r][slot] = pa[i];
-      sA[buf][1][r][slot] = pa[2 + i];
-      sB[buf][0][r][slot] = pb[i];
-      sB[buf][1][r][slot] = pb[2 + i];
+    for (int j = 0; j < 8; ++j) {
+      const int bl = 8 * wave + j, plane = bl >> 4, row0 = 16 * (bl & 15);
+      u16x8* dst = plane < 2 ? &dA[plane][row0][0] : &dB[plane - 2][row0][0];
+      __builtin_amdgcn_global_load_lds((const void*)(src[j] + kb),
+                                       (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
     }
   };
   const int fr = lane & 15, fk = lane >> 4;
@@ -242,51 +240,43 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int nsteps = a.Qs / KS;
-  // stage k lives in buffer k & 1: the next stage's global loads are issued
-  // before this stage's MFMAs and written to the other buffer after them, so
-  // one barrier per stage separates every write from the reads of that buffer.
-  // The last stage re-loads itself and writes the idle buffer, so the loop
-  // body has no branch around its loads and stores.
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int step = 0; step < nsteps; ++step) {
-    const int buf = step & 1;
-    load(min(step + 1, nsteps - 1) * KS);
-    // keep the loads ahead of the MFMAs (the scheduler would otherwise sink
-    // them next to their LDS stores and expose their latency)
+  // step s reads stage s & 1 and first starts the direct loads of step s + 1
+  // (the last step re-loads itself) into the other stage, whose last readers
+  // (step s - 1) the previous barrier has passed; every wave waits for its
+  // own loads before the barrier that ends the step
+  auto body = [&](int step, Stage& cA, Stage& cB, Stage& nA, Stage& nB) {
+    issue(min(step + 1, nsteps - 1) * KS, nA, nB);
     __builtin_amdgcn_sched_barrier(0);
-    // B fragments of the wave's four column blocks stay in registers while
-    // the eight row blocks stream through one A fragment pair at a time
     u16x8 bh[4], bl[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = wn + 16 * j + fr;
-      bh[j] = sB[buf][0][r][fk ^ swz(r)];
-      bl[j] = sB[buf][1][r][fk ^ swz(r)];
+      bh[j] = cB[0][r][fk ^ swz(r)];
+      bl[j] = cB[1][r][fk ^ swz(r)];
     }
-    auto rows = [&](int i) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
       const int r = wm + 16 * i + fr;
-      const u16x8 ah = sA[buf][0][r][fk ^ swz(r)], al = sA[buf][1][r][fk ^ swz(r)];
+      const u16x8 ah = cA[0][r][fk ^ swz(r)], al = cA[1][r][fk ^ swz(r)];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         acc[i][j] = mfma<F16>(ah, bh[j], acc[i][j]);
         acc[i][j] = mfma<F16>(ah, bl[j], acc[i][j]);
         acc[i][j] = mfma<F16>(al, bh[j], acc[i][j]);
       }
-    };
-    // the next stage goes to LDS halfway through the MFMAs (its loads have
-    // had half a step to land), so the barrier that ends the step does not
-    // also wait for the stores
-#pragma unroll
-    for (int i = 0; i < 4; ++i) rows(i);
-    __builtin_amdgcn_sched_barrier(0);
-    store(buf ^ 1);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int i = 4; i < 8; ++i) rows(i);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+  };
+  issue(0, sA0, sB0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int step = 0;
+  for (; step + 2 <= nsteps; step += 2) {
+    body(step, sA0, sB0, sA1, sB1);
+    body(step + 1, sA1, sB1, sA0, sB0);
   }
+  if (step < nsteps) body(step, sA0, sB0, sA1, sB1);
   float* const C = a.C;
   const long ldc = a.ldc;
   const int M = a.M, Nn = a.Nn;
