@@ -156,8 +156,8 @@ __global__ void split_rows_kernel(const double* in, long s_in_a, long s_in_b, in
 // Slab as a plain tiled GEMM over blocks of poles:
 //   X[(p, x)][(q, c)] = sum_Q R[p][x][Q] S[q][c][Q]
 // for p in a row block and q in a column block, with rows and columns
-// addressed through (pole, index) pairs. 256x256 output tiles, eight waves of
-// 128x64 (8x4 MFMA blocks each, two waves per SIMD), float32 accumulators.
+// addressed through (pole, index) pairs. 256x320 output tiles, eight waves of
+// 128x80 (8x5 MFMA blocks each, two waves per SIMD), float32 accumulators.
 struct XgemmArgs {
   const u16* Ah; const u16* Al; long sAp, sAx; int mA;   // row m: (m / mA) sAp + (m % mA) sAx
   const u16* Bh; const u16* Bl; long sBq, sBc; int nB;   // row n: (n / nB) sBq + (n % nB) sBc
@@ -166,7 +166,8 @@ struct XgemmArgs {
   int tiles_m, tiles_n;
 };
 
-constexpr int GT = 256;
+constexpr int GT = 256;    // slab tile rows: two waves of 128
+constexpr int GTN = 320;   // slab tile columns: four waves of 80
 
 // One launch carries up to XB problems of the same inner size (the mirrored
 // slabs of several block pairs): problem k owns workgroups [start[k],
@@ -178,18 +179,18 @@ struct XgemmBatch {
   int n;
 };
 
-// Eight waves (two per SIMD) share one 256 x 256 output tile, each wave a
-// 128 x 64 block of 8 x 4 MFMA tiles, so a SIMD can issue one wave's MFMAs
+// Eight waves (two per SIMD) share one 256 x 320 output tile, each wave a
+// 128 x 80 block of 8 x 5 MFMA tiles, so a SIMD can issue one wave's MFMAs
 // while the other waits on LDS or global memory.
 constexpr int XNT = 512;
 
 template <bool F16>
 __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
-  // two stages, each its own LDS arrays (hi, lo planes of A and of B): 128 KiB.
+  // two stages, each its own LDS arrays (hi, lo planes of A and of B): 144 KiB.
   // Separate arrays let the compiler see that the stage being read is not the
   // one the direct loads are filling, so it waits for those loads only where
   // the code says so (before the barrier that ends a step).
-  __shared__ u16x8 sA0[2][GT][KV], sB0[2][GT][KV], sA1[2][GT][KV], sB1[2][GT][KV];
+  __shared__ u16x8 sA0[2][GT][KV], sB0[2][GTN][KV], sA1[2][GT][KV], sB1[2][GTN][KV];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const long G = (long)gridDim.x;
@@ -199,57 +200,65 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
   const XgemmArgs& a = b.p[k];
   logical -= b.start[k];
   const int tm = (int)(logical / a.tiles_n), tn = (int)(logical % a.tiles_n);
-  const int m0 = tm * GT, n0 = tn * GT;
-  // direct-to-LDS loader: a stage is 64 blocks of 16 rows (block bl: plane
-  // bl / 16 of Ah, Al, Bh, Bl; rows 16 (bl % 16) ..); wave w fills blocks
-  // 8w .. 8w + 7. Lane l lands in LDS slot l % 4 of row l / 4 of its block,
-  // so it loads global vector (l % 4) ^ swz(row) of that row (the
+  const int m0 = tm * GT, n0 = tn * GTN;
+  // direct-to-LDS loader: a stage is 72 blocks of 16 rows (blocks 0-31: A
+  // plane bl / 16 of Ah, Al, rows 16 (bl % 16) ..; blocks 32-71: B plane
+  // (bl - 32) / 20 of Bh, Bl, rows 16 ((bl - 32) % 20) ..); wave w fills
+  // blocks 9w .. 9w + 8. Lane l lands in LDS slot l % 4 of row l / 4 of its
+  // block, so it loads global vector (l % 4) ^ swz(row) of that row (the
   // conflict-free layout of the fragment reads). Rows past M (N) read row
   // M - 1 (N - 1): they only feed outputs that are not stored.
-  const u16* src[8];
+  const u16* src[9];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int bl = 8 * wave + j, plane = bl >> 4;
-    const int r = 16 * (bl & 15) + (lane >> 2);
+  for (int j = 0; j < 9; ++j) {
+    const int bl = 9 * wave + j;
+    const bool isa = bl < 32;
+    const int b2 = isa ? bl : bl - 32;
+    const int plane = isa ? b2 >> 4 : b2 / 20, rb = isa ? b2 & 15 : b2 % 20;
+    const int r = 16 * rb + (lane >> 2);
     const int kvg = (lane & 3) ^ swz(r);
-    if (plane < 2) {
+    if (isa) {
       const int m = min(m0 + r, a.M - 1);
       src[j] = (plane == 0 ? a.Ah : a.Al) + (long)(m / a.mA) * a.sAp +
                (long)(m % a.mA) * a.sAx + 8 * kvg;
     } else {
       const int n = min(n0 + r, a.Nn - 1);
-      src[j] = (plane == 2 ? a.Bh : a.Bl) + (long)(n / a.nB) * a.sBq +
+      src[j] = (plane == 0 ? a.Bh : a.Bl) + (long)(n / a.nB) * a.sBq +
                (long)(n % a.nB) * a.sBc + 8 * kvg;
     }
   }
-  typedef u16x8 Stage[2][GT][KV];
-  auto issue = [&](int kb, Stage& dA, Stage& dB) {
+  typedef u16x8 StageA[2][GT][KV];
+  typedef u16x8 StageB[2][GTN][KV];
+  auto issue = [&](int kb, StageA& dA, StageB& dB) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int bl = 8 * wave + j, plane = bl >> 4, row0 = 16 * (bl & 15);
-      u16x8* dst = plane < 2 ? &dA[plane][row0][0] : &dB[plane - 2][row0][0];
+    for (int j = 0; j < 9; ++j) {
+      const int bl = 9 * wave + j;
+      const bool isa = bl < 32;
+      const int b2 = isa ? bl : bl - 32;
+      const int plane = isa ? b2 >> 4 : b2 / 20, row0 = 16 * (isa ? b2 & 15 : b2 % 20);
+      u16x8* dst = isa ? &dA[plane][row0][0] : &dB[plane][row0][0];
       __builtin_amdgcn_global_load_lds((const void*)(src[j] + kb),
                                        (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
     }
   };
   const int fr = lane & 15, fk = lane >> 4;
-  const int wm = (wave & 1) * 128, wn = (wave >> 1) * 64;
-  f4 acc[8][4];
+  const int wm = (wave & 1) * 128, wn = (wave >> 1) * 80;
+  f4 acc[8][5];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 5; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int nsteps = a.Qs / KS;
   // step s reads stage s & 1 and first starts the direct loads of step s + 1
   // (the last step re-loads itself) into the other stage, whose last readers
   // (step s - 1) the previous barrier has passed; every wave waits for its
   // own loads before the barrier that ends the step
-  auto body = [&](int step, Stage& cA, Stage& cB, Stage& nA, Stage& nB) {
+  auto body = [&](int step, StageA& cA, StageB& cB, StageA& nA, StageB& nB) {
     issue(min(step + 1, nsteps - 1) * KS, nA, nB);
     __builtin_amdgcn_sched_barrier(0);
-    u16x8 bh[4], bl[4];
+    u16x8 bh[5], bl[5];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 5; ++j) {
       const int r = wn + 16 * j + fr;
       bh[j] = cB[0][r][fk ^ swz(r)];
       bl[j] = cB[1][r][fk ^ swz(r)];
@@ -259,7 +268,7 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
       const int r = wm + 16 * i + fr;
       const u16x8 ah = cA[0][r][fk ^ swz(r)], al = cA[1][r][fk ^ swz(r)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 5; ++j) {
         acc[i][j] = mfma<F16>(ah, bh[j], acc[i][j]);
         acc[i][j] = mfma<F16>(ah, bl[j], acc[i][j]);
         acc[i][j] = mfma<F16>(al, bh[j], acc[i][j]);
@@ -283,7 +292,7 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 5; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + crow(lane, r);
@@ -778,7 +787,7 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
     g.nB = nc;
     g.M = nrow * N; g.Nn = ncol * nc; g.Qs = Qs;
     g.C = C; g.ldc = (long)ncol * nc;
-    g.tiles_m = (g.M + GT - 1) / GT; g.tiles_n = (g.Nn + GT - 1) / GT;
+    g.tiles_m = (g.M + GT - 1) / GT; g.tiles_n = (g.Nn + GTN - 1) / GTN;
     return g;
   };
   // one launch for the problems collected in b
