@@ -117,6 +117,18 @@ def test_fock_build_shapes(h, nmo, naux):
     assert np.array_equal(got, got.T)
 
 
+def test_fock_build_rejects_bad_sizes(h):
+    """The size checks run before any array is touched, so small buffers stand
+    in for the arrays of the rejected sizes."""
+    from paper_2106_03508_amd import agf2
+    a, b = dev(np.zeros(16)), dev(np.zeros(16))
+    for nphys, naux in ((46341, 1), (0, 4), (4, 0)):
+        st = h.lib.agf2_fock_build(h.h, nphys, naux, a.data_ptr(), a.data_ptr(), a.data_ptr(),
+                                   1.0, b.data_ptr())
+        assert st == -1, (nphys, naux, st)
+    assert "nphys" in agf2.load_library().agf2_last_error(h.h).decode()
+
+
 def _moments(seed=2, nmo=40, naux=60, npole=100, nocc=35):
     L = syn.df_tensor(seed, nmo, naux, 5)
     e, u = syn.random_poles(seed, nmo, npole, nocc)
