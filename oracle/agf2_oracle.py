@@ -589,6 +589,28 @@ def ip_ea(e_pole, u_pole, nocc_pole):
             w[nocc_pole - 1], w[nocc_pole])
 
 
+def spectral_function(e_pole, u_pole, omega, eta, weight=None):
+    """Broadened spectral function in the physical space (the simulated
+    photoelectron spectra of the artemisinin section, with a broadening
+    factor eta): A(w) = -1/pi Im Tr[P G(w + i eta)].
+
+    G(z) is the physical block of the resolvent of the extended Hamiltonian
+    whose eigenpairs the Dyson equation gives (`dyson_eq_eig`), so
+    G(z) = sum_l u_l u_l^T / (z - lam_l) and
+      A(w) = eta/pi sum_l w_l / ((w - lam_l)^2 + eta^2),
+      w_l  = sum_p P_p u[p, l]^2.
+    Reading: P = diag(weight) is a weight per physical orbital (a projection
+    such as the paper's atomic one, which needs basis data a synthetic
+    system lacks); weight None is the identity, the total spectrum."""
+    e_pole = np.asarray(e_pole, dtype=np.float64)
+    u_pole = np.asarray(u_pole, dtype=np.float64)
+    omega = np.asarray(omega, dtype=np.float64)
+    P = np.ones(u_pole.shape[0]) if weight is None else np.asarray(weight, np.float64)
+    w = np.sum(P[:, None] * u_pole * u_pole, axis=0)
+    d = omega[:, None] - e_pole[None, :]
+    return eta / np.pi * np.sum(w[None, :] / (d * d + eta * eta), axis=1)
+
+
 # ----------------------------------------------------------------------------
 # Outer self-consistency
 # ----------------------------------------------------------------------------

@@ -402,3 +402,64 @@ def test_sampled_elements_equal_full_moments():
     for k, (p, q) in enumerate(pairs):
         for m in range(4):
             assert abs(el[k, m] - full[m][p, q]) < 1e-13 * np.abs(full[m]).max()
+
+
+# ---------------------------------------------------------------- spectrum
+
+def _extended_system(seed=4, nmo=6, naux=12):
+    """A converged-looking extended Hamiltonian: the Fock loop's H_ext of a
+    small system, its eigenpairs and its physical block size."""
+    eps, L, nocc = small_system(seed, nmo, 2, naux)
+    h = O.synthetic_hcore(eps, L, nocc)
+    m = O.se_moments(L, eps, np.eye(nmo), nocc)
+    eo, vo = O.compress(m[0], m[1])
+    ev, vv = O.compress(m[2], m[3])
+    e_aux = np.concatenate([eo, ev])
+    v_aux = np.hstack([vo, vv])
+    fl = O.fock_loop(h, L, 2 * nocc, e_aux, v_aux, O.reference_density(nmo, nocc))
+    H = O.extended_hamiltonian(fl["fock"], e_aux + fl["shift"], v_aux)
+    return H, fl["e_pole"], fl["u_pole"], nmo
+
+
+def test_spectral_function_equals_resolvent_trace():
+    """-1/pi Im Tr of the physical block of ((w + i eta) - H_ext)^-1, each
+    frequency by a dense complex inverse, with and without a projection."""
+    H, lam, u, N = _extended_system()
+    eta = 0.2 / 27.211386
+    omega = np.linspace(lam.min() - 0.3, lam.max() + 0.3, 37)
+    P = np.linspace(0.2, 1.7, N)
+    for weight in (None, P):
+        got = O.spectral_function(lam, u, omega, eta, weight)
+        ref = np.empty_like(omega)
+        for k, w in enumerate(omega):
+            Gz = np.linalg.inv((w + 1j * eta) * np.eye(H.shape[0]) - H)[:N, :N]
+            Pm = np.ones(N) if weight is None else weight
+            ref[k] = -np.trace(Pm[:, None] * Gz).imag / np.pi
+        assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_spectral_function_sum_rule_and_projections():
+    """The integral over a frequency window equals the Lorentzian masses that
+    fall inside it (sum_l w_l (atan((b-lam)/eta) - atan((a-lam)/eta))/pi,
+    tending to Tr P = N); per-orbital projections add up to the total."""
+    H, lam, u, N = _extended_system(5)
+    eta = 0.01
+    a, b = lam.min() - 3.0, lam.max() + 3.0
+    omega = np.linspace(a, b, 400001)
+    A = O.spectral_function(lam, u, omega, eta)
+    integral = np.sum((A[1:] + A[:-1]) * 0.5 * np.diff(omega))
+    w = np.sum(u * u, axis=0)
+    inside = np.sum(w * (np.arctan((b - lam) / eta) - np.arctan((a - lam) / eta))) / np.pi
+    assert abs(integral - inside) < 1e-6 * N
+    assert abs(inside - N) < 0.01 * N
+    parts = sum(O.spectral_function(lam, u, omega[::1000], eta, np.eye(N)[p])
+                for p in range(N))
+    assert np.abs(parts - A[::1000]).max() < 1e-12 * A.max()
+
+
+def test_spectral_function_single_pole_is_a_lorentzian():
+    omega = np.linspace(-1.0, 1.5, 11)   # step 0.25: the pole lies on the grid
+    A = O.spectral_function(np.array([0.25]), np.array([[0.6]]), omega, 0.05)
+    ref = 0.36 * 0.05 / np.pi / ((omega - 0.25) ** 2 + 0.05 ** 2)
+    assert np.abs(A - ref).max() < 1e-14 * ref.max()
+    assert np.argmax(A) == np.argmin(np.abs(omega - 0.25))
