@@ -219,6 +219,28 @@ agf2_status agf2_energy_gf(agf2_handle_t handle, int nphys,
                            const double* e_se_vir, const double* v_se_vir,
                            double* e_1b, double* e_2b);
 
+/*
+ * Broadened spectral function of the Green's function in the physical space
+ * (the simulated photoelectron spectra of the application section, with a
+ * broadening factor eta):
+ *   A(omega_k) = -1/pi Im Tr[P G(omega_k + i eta)]
+ *              = eta/pi sum_l w_l / ((omega_k - e_pole[l])^2 + eta^2),
+ *   w_l = sum_p weight[p] u_pole[p][l]^2,
+ * G being the physical block of the resolvent of the extended Hamiltonian
+ * whose eigenpairs are the poles (the Dyson equation as an eigenproblem).
+ *   e_pole   device [npole] pole energies (any order).
+ *   u_pole   device [nphys][npole] physical amplitudes (row-major).
+ *   weight   device [nphys] weight per physical orbital (a projection), or
+ *            NULL for all ones (the total spectrum).
+ *   omega    device [nomega] frequencies; eta > 0, same unit (Ha).
+ *   A        device [nomega] output (1/Ha).
+ * Errors: AGF2_ERR_ARG for bad sizes, NULL pointers or eta not positive.
+ */
+agf2_status agf2_spectral_function(agf2_handle_t handle, int nphys, int npole,
+                                   const double* e_pole, const double* u_pole,
+                                   const double* weight, int nomega,
+                                   const double* omega, double eta, double* A);
+
 /* One system of a batched moment build (all pointers device, row-major,
  * float64; meaning as in agf2_build_moments). */
 typedef struct {

@@ -70,6 +70,7 @@ SIGNATURES = {
                             _DP, _IP, ctypes.POINTER(FockOpts)]),
     "agf2_energy_gf": (_I, [_P, _I, _P, _P, _P, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P,
                             _DP, _DP]),
+    "agf2_spectral_function": (_I, [_P, _I, _I, _P, _P, _P, _I, _P, _D, _P]),
     "agf2_run_opts_default": (None, [ctypes.POINTER(RunOpts)]),
     "agf2_run": (_I, [_P, ctypes.POINTER(RunOpts), _I, _I, _P, _P, _P, _I, _P,
                       ctypes.POINTER(IterRecord), _IP, _IP, _P, _P, _IP, _P]),
@@ -282,6 +283,20 @@ def agf2_fock_loop(h: Handle, L, hcore, nelec: int, e_se, v_se, rdm1, opts: Fock
         h._check(st)
     return dict(fock=fock, e_pole=e_pole, u_pole=u_pole, nocc_pole=nocc.value, mu=mu.value,
                 shift=shift.value, n_cycle=ncyc.value, converged=converged, rdm1=rdm1)
+
+
+def agf2_spectral_function(h: Handle, e_pole, u_pole, omega, eta, weight=None, out=None):
+    """A[k] = -1/pi Im Tr[P G(omega_k + i eta)] of the poles; weight [nphys]
+    (a projection) or None for the total spectrum."""
+    nphys, npole = u_pole.shape
+    out = h.empty(omega.shape[0]) if out is None else out
+    d = h.device
+    wp = None if weight is None else _ptr(weight, "weight", d)
+    h._check(h.lib.agf2_spectral_function(h.h, nphys, npole, _ptr(e_pole, "e_pole", d),
+                                          _ptr(u_pole, "u_pole", d), wp, omega.shape[0],
+                                          _ptr(omega, "omega", d), float(eta),
+                                          _ptr(out, "A", d)))
+    return out
 
 
 def agf2_energy_gf(h: Handle, hcore, fock, rdm1, e_pole, u_pole, nocc_pole, e_se_occ, v_se_occ,

@@ -88,6 +88,8 @@ Handle::~Handle() {
   for (auto& b : ws_fock) b.release();
   for (auto& b : ws_misc) b.release();
   for (auto& b : ws_run) b.release();
+  for (auto& b : ws_mlp) b.release();
+  ws_spec.release();
   ws_red.release();
   if (host_red) (void)hipHostFree(host_red);
   if (blas) rocblas_destroy_handle(blas);
@@ -968,6 +970,18 @@ agf2_status agf2_energy_gf(agf2_handle_t hh, int nphys, const double* hcore, con
                  "NULL auxiliary argument");
     energy_impl(h, nphys, hcore, fock, rdm1, npole, nocc_pole, e_pole, u_pole, naux_occ,
                 e_se_occ, v_se_occ, naux_vir, e_se_vir, v_se_vir, e_1b, e_2b);
+  });
+}
+
+agf2_status agf2_spectral_function(agf2_handle_t hh, int nphys, int npole,
+                                   const double* e_pole, const double* u_pole,
+                                   const double* weight, int nomega, const double* omega,
+                                   double eta, double* A) {
+  return guarded(hh, [&](Handle& h) {
+    AGF2_REQUIRE(nphys >= 1 && npole >= 1 && nomega >= 0, "bad sizes");
+    AGF2_REQUIRE(eta > 0.0 && std::isfinite(eta), "eta must be positive");
+    AGF2_REQUIRE(e_pole && u_pole && (nomega == 0 || (omega && A)), "NULL argument");
+    spectral_function(h, nphys, npole, e_pole, u_pole, weight, nomega, omega, eta, A);
   });
 }
 

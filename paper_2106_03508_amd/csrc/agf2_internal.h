@@ -184,6 +184,11 @@ void build_moments(Handle& h, agf2_precision prec, int N, int Q, const double* L
                    int nocc, const double* e, const double* u, double* m0o, double* m1o,
                    double* m0v, double* m1v);
 
+// Broadened spectral function of the poles (spectrum.hip).
+void spectral_function(Handle& h, int nphys, int npole, const double* e_pole,
+                       const double* u_pole, const double* weight, int nomega,
+                       const double* omega, double eta, double* A);
+
 struct BatchPlan;   // batched moment build (moments_batched.hip)
 void destroy_batch_plan(BatchPlan* p);
 
@@ -204,6 +209,7 @@ struct Handle {
   DevBuf ws_misc[8];
   DevBuf ws_run[8];
   DevBuf ws_mlp[2];   // warm-start loss partials and prediction scratch
+  DevBuf ws_spec;     // spectral function: pole weights
   DevBuf ws_red;
   double* host_red = nullptr;   // pinned scratch for small reductions
   size_t host_red_n = 0;
