@@ -94,6 +94,10 @@ SMALL = dict(nmo=24, nocc=5, naux=80)          # oracle runs to convergence in s
 MEDIUM = dict(nmo=200, nocc=40, naux=700)      # double-zeta-molecule-like
 LARGE = dict(nmo=1000, nocc=76, naux=3500)     # ~1000 orbitals, artemisinin-like nocc
 EVAL400 = dict(nmo=400, nocc=80, naux=1400)    # warm-start evaluation size
+# the orbital and correlated-electron counts of the paper's timed runs
+# (aug-cc-pVDZ guanine and artemisinin); naux = 3.5 nmo assumed
+GUANINE = dict(nmo=298, nocc=39, naux=1043)
+ARTEMISININ = dict(nmo=658, nocc=76, naux=2303)
 
 
 def batch_shapes(nsys: int = 64, seed0: int = 1000, nmo_lo: int = 40, nmo_hi: int = 160):
