@@ -9,7 +9,8 @@
  *   - their compression to auxiliaries by one block-Lanczos step,
  *   - the Fock loop (extended Fock matrix, chemical potential, density),
  *   - the Galitskii-Migdal energy,
- *   - the outer self-consistent loop built from the calls above.
+ *   - the outer self-consistent loop built from the calls above,
+ *   - the broadened spectral function of the resulting poles.
  *
  * Conventions (all entry points):
  *   - Arrays are row-major float64 unless stated otherwise.
