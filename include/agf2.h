@@ -53,9 +53,10 @@ typedef enum {
  * tensors are formed in float64, rounded to float32 and stored as 16-bit
  * pairs x ~ hi + lo; the integral slabs take the products hi*hi + hi*lo +
  * lo*hi on the 16-bit MFMA pipe with float32 accumulation, the moment
- * contraction takes all four products, and float32 partial sums over bounded
- * chunks are added into float64 with Kahan compensation. Compression, the
- * Fock loop and the energy are float64 in every mode. */
+ * contraction takes all four products (hi*hi and the cross products in
+ * separate float32 sums), and those float32 sums over chunks of 256 columns
+ * are added into float64 sums. Compression, the Fock loop and the energy are
+ * float64 in every mode. */
 typedef enum {
   AGF2_FP64 = 0,        /* float64 operands, FP64 MFMA, float64 accumulation  */
   AGF2_SPLIT_BF16 = 1,  /* bf16 pairs (16 significant bits per value)         */
