@@ -22,6 +22,11 @@
  *   - Every call returns an agf2_status; AGF2_OK is 0 and errors are
  *     negative. agf2_last_error() gives a message for the last failure on the
  *     handle. No C++ exception crosses this boundary.
+ *   - Every float64 input array of an entry point is scanned on the device
+ *     before use; a NaN or an infinity in any of them returns AGF2_ERR_ARG
+ *     (the message names the array) and nothing is computed. The scan reads
+ *     each input once (about 6 ms for a 28 GB DF tensor). float32 arrays of
+ *     the warm-start network's calls are not scanned.
  *   - A handle must not be used by two threads at once. It owns a device
  *     workspace that grows on demand and is freed by agf2_destroy().
  *
@@ -187,8 +192,11 @@ void agf2_fock_opts_default(agf2_fock_opts* opts);
  *   u_pole     device [nphys][nphys + naux_se] out: physical amplitudes
  *   nocc_pole, mu, shift, n_cycle   host outputs
  *   opts       host, NULL for defaults
- * Returns AGF2_ERR_NO_CONVERGE (outputs hold the last cycle) when the cycle
- * limit is hit, AGF2_ERR_NELEC when nelec is out of range.
+ * Returns AGF2_ERR_NO_CONVERGE when the cycle limit is hit: the shift is
+ * then fitted (to tol_nelec) at the last Fock matrix, and the outputs hold
+ * that matrix, the auxiliary energies shifted by that fit, the poles of that
+ * extended Hamiltonian (exact eigenpairs) and their density. AGF2_ERR_NELEC
+ * when nelec is out of range.
  */
 agf2_status agf2_fock_loop(agf2_handle_t handle, int nphys, int naux,
                            const double* Lpq, const double* hcore, int nelec,
@@ -291,6 +299,7 @@ void agf2_run_opts_default(agf2_run_opts* opts);
 typedef struct {
   int iter;                      /* 0 = built from the mean-field poles    */
   int nocc_pole, npole, fock_cycles, warm;
+  int fock_converged;            /* 1 if this iteration's Fock loop converged */
   double e_1b, e_2b, e_tot;      /* Ha                                     */
   double ip, ea, w_ip, w_ea;     /* IP = -(highest occupied pole), EA,
                                     and their quasiparticle weights        */
@@ -307,7 +316,10 @@ typedef struct {
  * (starting from the previous density; 2 * diag(1_occ) at first), evaluates
  * the Galitskii-Migdal energy and IP/EA, and builds the next moments from the
  * nphys + 2 nphys poles. Converged when |dE| < conv_tol and max(|dIP|,
- * |dEA|) < conv_tol_ipea.
+ * |dEA|) < conv_tol_ipea. An iteration whose Fock loop reaches its cycle
+ * limit ends the run: its record has fock_converged = 0, the outputs hold
+ * its Green's function and density, and the call returns
+ * AGF2_ERR_NO_CONVERGE.
  *   Lpq device [naux][nphys][nphys]; hcore device [nphys][nphys];
  *   e_mf device [nphys]; nocc doubly occupied orbitals (nelec = 2 nocc).
  *   dm_init    device [4][nphys][nphys] or NULL: a correction added to the
@@ -325,6 +337,41 @@ agf2_status agf2_run(agf2_handle_t handle, const agf2_run_opts* opts,
                      const double* dm_init, agf2_iter_record* records,
                      int* n_records, int* converged, double* e_pole,
                      double* u_pole, int* nocc_pole, double* rdm1);
+
+/*
+ * Checkpoint and resume of agf2_run. The state between two iterations (the
+ * index of the next iteration, the current Green's function poles, the
+ * density, the previous moments kept for damping, the moment DIIS history
+ * and the last energy, IP and EA of the convergence test) is written to a
+ * host buffer of agf2_run_state_bytes(nphys, opts->diis_space) bytes (-1 for
+ * bad arguments). A run continued from a saved state with the same inputs
+ * and options takes exactly the iterations an uninterrupted agf2_run would
+ * have taken, with bitwise equal results.
+ *
+ * agf2_run_resume takes the arguments of agf2_run and:
+ *   state_in       host, NULL: start at iteration 0 (dm_init applies); else
+ *                  continue from this saved state (dm_init is ignored).
+ *                  AGF2_ERR_ARG if it was saved for another nphys or
+ *                  diis_space or is not a state at all.
+ *   state_out      host, NULL or a buffer of agf2_run_state_bytes: the state
+ *                  after the last iteration of this call (written on return
+ *                  unless an error other than AGF2_ERR_NO_CONVERGE occurs).
+ *   max_iter_call  > 0: stop after this many iterations in this call (the
+ *                  call then returns AGF2_OK with *converged = 0 unless the
+ *                  run converged or failed); <= 0: no limit but max_iter.
+ * records receives this call's iterations only (their iter fields continue
+ * the count); it must hold max_iter + 1 records. max_iter counts iterations
+ * from iteration 0 of the whole run.
+ */
+long agf2_run_state_bytes(int nphys, int diis_space);
+agf2_status agf2_run_resume(agf2_handle_t handle, const agf2_run_opts* opts,
+                            int nphys, int naux, const double* Lpq,
+                            const double* hcore, const double* e_mf, int nocc,
+                            const double* dm_init, const void* state_in,
+                            void* state_out, int max_iter_call,
+                            agf2_iter_record* records, int* n_records,
+                            int* converged, double* e_pole, double* u_pole,
+                            int* nocc_pole, double* rdm1);
 
 /*
  * Kernel timing (tracing aid, not part of the method). When enabled, the

@@ -371,7 +371,7 @@ def _solve(F, e_aux, v_aux, shift, nelec):
 
 
 def fit_shift(F, e_aux, v_aux, nelec, shift0=0.0, bracket=2.0, tol=1e-10,
-              step0=0.01, max_iter=100):
+              step0=0.01, max_iter=200):
     """Reading of the chemical-potential condition (electron number kept
     exact in a non-idempotent density): shift every auxiliary energy by a
     common Delta until the aufbau count equals nelec.
@@ -380,9 +380,8 @@ def fit_shift(F, e_aux, v_aux, nelec, shift0=0.0, bracket=2.0, tol=1e-10,
     Delta (the sum of the n lowest eigenvalues is concave in Delta and its
     derivative is n - c_n/2), so the root of g(Delta) = c_n(Delta) - nelec is
     bracketed by stepping away from shift0 (step0, doubling, never beyond
-    shift0 +- bracket) and then refined by regula falsi with the Illinois
-    modification, stopping when |g| < tol. If the aufbau picks another n at
-    the root, repeat with that n.
+    shift0 +- bracket) and then found by bisection, stopping when |g| < tol.
+    If the aufbau picks another n at the root, repeat with that n.
     Returns (shift, n_eig) with n_eig the number of eigensolves used."""
     n_eig = 1
     lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift0, nelec)
@@ -400,7 +399,6 @@ def fit_shift(F, e_aux, v_aux, nelec, shift0=0.0, bracket=2.0, tol=1e-10,
         direction = 1.0 if g0 < 0 else -1.0
         a, ga = shift, g0
         step = step0
-        b, gb = a, ga
         while True:
             b = shift + direction * min(step, bracket)
             gb = g(b); n_eig += 1
@@ -409,29 +407,23 @@ def fit_shift(F, e_aux, v_aux, nelec, shift0=0.0, bracket=2.0, tol=1e-10,
             a, ga = b, gb
             step *= 2.0
         if (gb > 0) == (ga > 0) and gb != 0.0:
-            shift = b          # no sign change inside the allowed bracket
+            x = b              # no sign change inside the allowed bracket
         else:
-            # Illinois regula falsi on [a, b]
-            side = 0
+            # bisection on [a, b]; g(a) and g(b) have opposite signs
             x = b
             for _ in range(max_iter):
-                if gb == 0.0:
+                if gb == 0.0 or abs(gb) < tol:
                     x = b
                     break
-                x = b - gb * (b - a) / (gb - ga)
+                x = 0.5 * (a + b)
                 gx = g(x); n_eig += 1
                 if abs(gx) < tol:
                     break
-                if (gx > 0) == (gb > 0):
-                    b, gb = x, gx
-                    if side == -1:
-                        ga *= 0.5
-                    side = -1
+                if (gx > 0) == (ga > 0):
+                    a, ga = x, gx
                 else:
-                    a, ga = b, gb
                     b, gb = x, gx
-                    side = +1
-            shift = x
+        shift = x
         lam, u, n_new, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
         n_eig += 1
         if n_new == n:
@@ -440,47 +432,23 @@ def fit_shift(F, e_aux, v_aux, nelec, shift0=0.0, bracket=2.0, tol=1e-10,
     return shift, n_eig
 
 
-def shift_derivative(lam, u, n):
-    """First-order response of the occupied physical density to the common
-    auxiliary shift Delta, at a fixed number n of occupied poles.
-
-    Reading: the extended Hamiltonian depends on Delta through Delta times
-    the projector A = 1 - P onto the auxiliary space, so first-order
-    perturbation theory of its eigenvectors gives, with c_l = u[:, l] the
-    physical part of eigenvector l and P_ij = c_i . c_j (i occupied, j
-    virtual), M_ij = P_ij / (lam_j - lam_i):
-        dD/dDelta = 2 (C_o M C_v^T + C_v M^T C_o^T),
-        dN/dDelta = tr(dD/dDelta) = 4 sum_ij M_ij P_ij  (> 0).
-    Rotations among the occupied poles leave D unchanged and drop out.
-    Returns (dN, dD)."""
-    Co, Cv = u[:, :n], u[:, n:]
-    P = Co.T @ Cv
-    M = P / (lam[None, n:] - lam[:n, None])
-    G = Co @ M @ Cv.T
-    return 4.0 * np.sum(M * P), 2.0 * (G + G.T)
-
-
 def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
-              max_cycle=50, bracket=2.0, shift0=0.0, diis_space=8, newton_max=1e-3):
+              max_cycle=50, bracket=2.0, shift0=0.0, diis_space=8, step0=0.01):
     """Density relaxation with the chemical potential held at the right
     electron number (relaxation passage after the self-consistency
     discussion), on the compressed extended Hamiltonian.
 
-    Each cycle: Delta fitted at the current F; eigendecomposition of
-    [[F, v], [v^T, diag(e + Delta)]]; aufbau; D = 2 sum_{l<n*} u_l u_l^T;
-    stop when the norm (Frobenius) of the change of D is below tol_rdm1, else
-    the next F is
-    F[D], DIIS-extrapolated with the fixed-point residual F[D] - F as error.
-    Reading (how Delta is fitted while the density still moves): when the
-    count at the current Delta misses the cycle's tolerance by a Newton step
-    |g / (dN/dDelta)| <= newton_max, Delta takes that step and D is taken to
-    first order in it (shift_derivative) instead of refitting; otherwise, and
-    always for the returned density, Delta is fitted to tolerance and D comes
-    from the eigendecomposition at the fitted Delta.
+    Each cycle: Delta fitted at the current F to |count - nelec| < tol_nelec
+    (fit_shift); eigendecomposition of [[F, v], [v^T, diag(e + Delta)]];
+    aufbau; D = 2 sum_{l<n*} u_l u_l^T; stop when the Frobenius norm of the
+    change of D is below tol_rdm1, else the next F is F[D], DIIS-extrapolated
+    with the fixed-point residual F[D] - F as error.
     Reading: the tolerance bounds the whole change of the density matrix, so
     the energy it leaves unconverged does not grow with the basis size.
     The returned F is the one diagonalised last, so the returned poles are
-    exact eigenpairs of the returned extended Hamiltonian.
+    exact eigenpairs of the returned extended Hamiltonian. When max_cycle is
+    reached first, the shift is fitted once more at the last F and the poles
+    and density returned are those of that F (converged False).
     Returns a dict."""
     F = fock_matrix(h, L, D)
     shift = shift0
@@ -488,55 +456,31 @@ def fock_loop(h, L, nelec, e_aux, v_aux, D, tol_rdm1=1e-8, tol_nelec=1e-10,
     converged = False
     diis = DIIS(diis_space) if diis_space else None
     N = F.shape[0]
-    err_prev = np.inf
     for cycle in range(1, max_cycle + 1):
-        # the electron count is fitted to tol_nelec once the density has
-        # settled; earlier cycles, whose density is still moving, to
-        # 0.01 x its last change (at most 1e-6)
-        tol_c = max(tol_nelec, min(1e-6, 1e-2 * err_prev))
+        shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift, bracket=bracket,
+                              tol=tol_nelec, step0=step0)
+        n_eig += ne
         lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
         n_eig += 1
-        g0 = cnt - nelec
-        first_order = False
-        if abs(g0) >= tol_c:
-            with np.errstate(divide="ignore", invalid="ignore"):
-                dN, dD = shift_derivative(lam, u, n)
-            # no step when the derivative is not finite and positive (an
-            # occupied and a virtual pole at the same energy)
-            step = -g0 / dN if (np.isfinite(dN) and dN > 0) else np.inf
-            if abs(step) <= newton_max:
-                uo = u[:, :n]
-                D_new = 2.0 * uo @ uo.T + step * dD
-                shift += step
-                first_order = True
-            else:
-                shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift,
-                                      bracket=bracket, tol=tol_c)
-                n_eig += ne
-                lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
-                n_eig += 1
-        if not first_order:
-            uo = u[:, :n]
-            D_new = 2.0 * uo @ uo.T
+        uo = u[:, :n]
+        D_new = 2.0 * uo @ uo.T
         err = np.linalg.norm(D_new - D)
-        err_prev = err
         D = D_new
         if err < tol_rdm1:
-            if first_order or tol_c > tol_nelec:
-                # the returned density meets tol_nelec (same F)
-                shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift,
-                                      bracket=bracket, tol=tol_nelec)
-                n_eig += ne
-                lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
-                n_eig += 1
-                uo = u[:, :n]
-                D = 2.0 * uo @ uo.T
             converged = True
             break
         F_new = fock_matrix(h, L, D)
         if diis is not None:
             F_new = diis.update(F_new, err=F_new - F).reshape(N, N)
         F = F_new
+    if not converged:
+        shift, ne = fit_shift(F, e_aux, v_aux, nelec, shift0=shift, bracket=bracket,
+                              tol=tol_nelec, step0=step0)
+        n_eig += ne
+        lam, u, n, cnt, mu = _solve(F, e_aux, v_aux, shift, nelec)
+        n_eig += 1
+        uo = u[:, :n]
+        D = 2.0 * uo @ uo.T
     return dict(e_pole=lam, u_pole=u, nocc_pole=n, mu=mu, shift=shift,
                 rdm1=D, fock=F, n_cycle=cycle, n_eig=n_eig, converged=converged,
                 nelec=cnt)
@@ -665,7 +609,8 @@ def run_agf2(h, L, eps, nocc, max_iter=20, conv_tol=1e-8, conv_tol_ipea=1e-7,
     from the current poles, extrapolates them (DIIS), compresses the lesser
     and greater parts to N auxiliaries each, relaxes the density in the Fock
     loop, and evaluates the energy and IP/EA. Converged when the energy
-    changes by less than conv_tol and IP/EA by less than conv_tol_ipea."""
+    changes by less than conv_tol and IP/EA by less than conv_tol_ipea.
+    Stops unconverged when a Fock loop reaches its cycle limit."""
     fock_opts = dict(fock_opts or {})
     N = eps.shape[0]
     nelec = 2 * nocc
@@ -700,6 +645,8 @@ def run_agf2(h, L, eps, nocc, max_iter=20, conv_tol=1e-8, conv_tol_ipea=1e-7,
         hist.append(rec)
         if verbose:
             print(rec)
+        if not fl["converged"]:
+            break              # the density of this iteration is not relaxed
         if prev is not None:
             if (abs(rec["etot"] - prev["etot"]) < conv_tol
                     and max(abs(ip - prev["ip"]), abs(ea - prev["ea"])) < conv_tol_ipea):

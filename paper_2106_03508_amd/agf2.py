@@ -45,7 +45,7 @@ class RunOpts(ctypes.Structure):
 
 class IterRecord(ctypes.Structure):
     _fields_ = [("iter", _I), ("nocc_pole", _I), ("npole", _I), ("fock_cycles", _I),
-                ("warm", _I), ("e_1b", _D), ("e_2b", _D), ("e_tot", _D), ("ip", _D),
+                ("warm", _I), ("fock_converged", _I), ("e_1b", _D), ("e_2b", _D), ("e_tot", _D), ("ip", _D),
                 ("ea", _D), ("w_ip", _D), ("w_ea", _D), ("mu", _D), ("shift", _D),
                 ("t_moments", _D), ("t_compress", _D), ("t_fock", _D), ("t_energy", _D)]
 
@@ -74,6 +74,9 @@ SIGNATURES = {
     "agf2_run_opts_default": (None, [ctypes.POINTER(RunOpts)]),
     "agf2_run": (_I, [_P, ctypes.POINTER(RunOpts), _I, _I, _P, _P, _P, _I, _P,
                       ctypes.POINTER(IterRecord), _IP, _IP, _P, _P, _IP, _P]),
+    "agf2_run_state_bytes": (ctypes.c_long, [_I, _I]),
+    "agf2_run_resume": (_I, [_P, ctypes.POINTER(RunOpts), _I, _I, _P, _P, _P, _I, _P, _P, _P,
+                             _I, ctypes.POINTER(IterRecord), _IP, _IP, _P, _P, _IP, _P]),
     "agf2_mlp_create": (_I, [_P, ctypes.POINTER(_P)]),
     "agf2_mlp_destroy": (_I, [_P]),
     "agf2_mlp_set_params": (_I, [_P, _P, _P]),
@@ -381,6 +384,50 @@ def agf2_run(h: Handle, L, hcore, e_mf, nocc: int, opts: RunOpts = None, dm_init
     return dict(history=history, converged=bool(conv.value), e_pole=e_pole[:npole],
                 u_pole=u_pole.view(-1)[:nphys * npole].view(nphys, npole),
                 nocc_pole=nocc_pole.value, rdm1=rdm1)
+
+
+def agf2_run_resume(h: Handle, L, hcore, e_mf, nocc: int, opts: RunOpts = None, dm_init=None,
+                    state_in=None, save_state=True, max_iter_call=0,
+                    raise_on_no_converge=False):
+    """agf2_run continued from a saved state (state_in: numpy uint8 array from
+    an earlier call, or None to start at iteration 0), stopping after
+    max_iter_call iterations (0: no limit). Returns the agf2_run dict plus
+    "state" (numpy uint8, the state after this call's last iteration) and
+    "status"."""
+    import numpy as np
+    naux, nphys, _ = L.shape
+    opts = run_opts() if opts is None else opts
+    nbytes = h.lib.agf2_run_state_bytes(nphys, opts.diis_space)
+    if nbytes < 0:
+        raise ValueError("bad nphys or diis_space")
+    sin = None
+    if state_in is not None:
+        sin = np.ascontiguousarray(state_in, dtype=np.uint8)
+        if sin.shape != (nbytes,):
+            raise ValueError(f"state_in must hold {nbytes} bytes")
+    sout = np.empty(nbytes, dtype=np.uint8) if save_state else None
+    recs = (IterRecord * (opts.max_iter + 1))()
+    nrec = ctypes.c_int(0)
+    conv = ctypes.c_int(0)
+    nocc_pole = ctypes.c_int(0)
+    e_pole = h.empty(3 * nphys)
+    u_pole = h.empty(nphys, 3 * nphys)
+    rdm1 = h.empty(nphys, nphys)
+    d = h.device
+    st = h.lib.agf2_run_resume(
+        h.h, ctypes.byref(opts), nphys, naux, _ptr(L, "L", d), _ptr(hcore, "hcore", d),
+        _ptr(e_mf, "e_mf", d), int(nocc), None if dm_init is None else _ptr(dm_init, "dm_init", d),
+        None if sin is None else sin.ctypes.data, None if sout is None else sout.ctypes.data,
+        int(max_iter_call), recs, ctypes.byref(nrec), ctypes.byref(conv),
+        _ptr(e_pole, "e_pole", d), _ptr(u_pole, "u_pole", d), ctypes.byref(nocc_pole),
+        _ptr(rdm1, "rdm1", d))
+    if st != 0 and (st != -5 or raise_on_no_converge):
+        h._check(st)
+    history = [{f: getattr(recs[i], f) for f, _ in IterRecord._fields_} for i in range(nrec.value)]
+    npole = history[-1]["npole"] if history else nphys
+    return dict(history=history, converged=bool(conv.value), e_pole=e_pole[:npole],
+                u_pole=u_pole.view(-1)[:nphys * npole].view(nphys, npole),
+                nocc_pole=nocc_pole.value, rdm1=rdm1, state=sout, status=st)
 
 
 # ---------------------------------------------------------------- warm start

@@ -77,6 +77,44 @@ static void prof_flush(Handle& h) {
   h.prof_pending.clear();
 }
 
+// One bit of *flag per array: set when any element is NaN or infinite (a
+// vote per wave, one atomic per wave that saw one).
+__global__ __launch_bounds__(256) void nonfinite_kernel(long n, const double* x,
+                                                        unsigned bit, unsigned* flag) {
+  int bad = 0;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+    bad |= !(std::fabs(x[i]) <= 1.7976931348623157e308);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u << bit);
+}
+
+FiniteCheck& FiniteCheck::add(const double* p, long n, const char* what) {
+  if (p && n > 0) {
+    if (ptr.size() >= 32) throw Error{AGF2_ERR_ARG, "internal: too many arrays in one check"};
+    ptr.push_back(p);
+    len.push_back(n);
+    name.push_back(what);
+  }
+  return *this;
+}
+
+void FiniteCheck::run() {
+  if (ptr.empty()) return;
+  unsigned* flag = h.ws_check.as<unsigned>(1);
+  AGF2_HIP(hipMemsetAsync(flag, 0, sizeof(unsigned), h.stream));
+  for (size_t k = 0; k < ptr.size(); ++k) {
+    const int nb = (int)std::max<long>(1, std::min<long>((len[k] + 255) / 256, 2048));
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(nb), dim3(256), 0, h.stream, len[k], ptr[k],
+                       (unsigned)k, flag);
+    AGF2_CHECK_LAUNCH();
+  }
+  unsigned hf = 0;
+  AGF2_HIP(hipMemcpyAsync(&hf, flag, sizeof(unsigned), hipMemcpyDeviceToHost, h.stream));
+  AGF2_HIP(hipStreamSynchronize(h.stream));
+  for (size_t k = 0; k < ptr.size(); ++k)
+    if (hf & (1u << k))
+      throw Error{AGF2_ERR_ARG, name[k] + " holds a non-finite value (NaN or infinity)"};
+}
+
 Handle::~Handle() {
   (void)hipDeviceSynchronize();
   destroy_batch_plan(batch);
@@ -91,6 +129,7 @@ Handle::~Handle() {
   for (auto& b : ws_mlp) b.release();
   ws_spec.release();
   ws_red.release();
+  ws_check.release();
   if (host_red) (void)hipHostFree(host_red);
   if (blas) rocblas_destroy_handle(blas);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -641,28 +680,28 @@ FockLoopResult fock_loop_impl(Handle& h, int nphys, int naux, const double* Lpq,
   int cycle = 0;
   Aufbau a;
   double err_prev = INFINITY;
+  // D = 2 sum_{l < n*} phi_l phi_l^T (physical block) of the last solve into Dn
+  auto density = [&]() {
+    a = aufbau(fl.n, fl.hlam, fl.hw, (double)nelec);
+    Gemm g;
+    g.M = N; g.N = N; g.K = a.n;
+    g.A = fl.H; g.sAm = 1; g.sAk = fl.n;
+    g.B = fl.H; g.sBn = 1; g.sBk = fl.n;
+    g.C = Dn; g.sCm = N; g.sCn = 1; g.alpha = 2.0;
+    if (a.n > 0) gemm_f64(g, s);
+    else AGF2_HIP(hipMemsetAsync(Dn, 0, nn * sizeof(double), s));
+  };
+  // fit the shift at F to tolerance tol, then the density at the fitted shift
+  auto fit_and_density = [&](double tol) {
+    d = fl.fit_shift(F, d, o, tol);
+    if (!(fl.solved_shift == d && fl.solved_F == F)) fl.solve(F, d);
+    density();
+  };
   for (cycle = 1; cycle <= o.max_cycle; ++cycle) {
     // the electron count is fitted to tol_nelec once the density has
     // settled; earlier cycles, whose density is still moving, to 0.01 x its
     // last change (at most 1e-6)
     const double tol_c = std::max(o.tol_nelec, std::min(1e-6, 1e-2 * err_prev));
-    // D = 2 sum_{l < n*} phi_l phi_l^T (physical block) of the last solve into Dn
-    auto density = [&]() {
-      a = aufbau(fl.n, fl.hlam, fl.hw, (double)nelec);
-      Gemm g;
-      g.M = N; g.N = N; g.K = a.n;
-      g.A = fl.H; g.sAm = 1; g.sAk = fl.n;
-      g.B = fl.H; g.sBn = 1; g.sBk = fl.n;
-      g.C = Dn; g.sCm = N; g.sCn = 1; g.alpha = 2.0;
-      if (a.n > 0) gemm_f64(g, s);
-      else AGF2_HIP(hipMemsetAsync(Dn, 0, nn * sizeof(double), s));
-    };
-    // fit the shift at F to tolerance tol, then the density at the fitted shift
-    auto fit_and_density = [&](double tol) {
-      d = fl.fit_shift(F, d, o, tol);
-      if (!(fl.solved_shift == d && fl.solved_F == F)) fl.solve(F, d);
-      density();
-    };
     // Solve at the current shift. If the count misses tol_c by a Newton step
     // of at most kNewtonMax, take that step and the density to first order in
     // it (no further eigensolve); otherwise fit the shift to tol_c.
@@ -707,6 +746,13 @@ FockLoopResult fock_loop_impl(Handle& h, int nphys, int naux, const double* Lpq,
     diis.update(Fn, Dn);
     AGF2_HIP(hipMemcpyAsync(F, Fn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
     fl.invalidate();
+  }
+  if (!converged) {
+    // cycle limit: the last F has not been diagonalised yet. Fit the shift
+    // there, so that the returned poles are eigenpairs of the returned Fock
+    // matrix and shifted auxiliaries, and the density is that of these poles.
+    fit_and_density(o.tol_nelec);
+    AGF2_HIP(hipMemcpyAsync(rdm1, Dn, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   if (cycle > o.max_cycle) cycle = o.max_cycle;
   AGF2_HIP(hipMemcpyAsync(fock, F, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -898,6 +944,11 @@ agf2_status agf2_build_moments(agf2_handle_t hh, agf2_precision prec, int nphys,
                  "need 1 <= nocc_pole < npole");
     AGF2_REQUIRE(Lpq && e_pole && u_pole && m0_occ && m1_occ && m0_vir && m1_vir,
                  "NULL array argument");
+    FiniteCheck(h)
+        .add(Lpq, (long)naux * nphys * nphys, "Lpq")
+        .add(e_pole, npole, "e_pole")
+        .add(u_pole, (long)nphys * npole, "u_pole")
+        .run();
     build_moments(h, prec, nphys, naux, Lpq, npole, nocc_pole, e_pole, u_pole, m0_occ, m1_occ,
                   m0_vir, m1_vir);
   });
@@ -911,6 +962,8 @@ agf2_status agf2_fock_build(agf2_handle_t hh, int nphys, int naux, const double*
     AGF2_REQUIRE(nphys <= 46340, "nphys must be <= 46340");
     AGF2_REQUIRE(Lpq && hcore && rdm1 && fock, "NULL array argument");
     AGF2_REQUIRE(fock != hcore && fock != rdm1, "fock may not alias an input");
+    const long nn = (long)nphys * nphys;
+    FiniteCheck(h).add(Lpq, naux * nn, "Lpq").add(hcore, nn, "hcore").add(rdm1, nn, "rdm1").run();
     fock_build(h, nphys, naux, Lpq, hcore, rdm1, alpha, fock);
   });
 }
@@ -922,6 +975,8 @@ agf2_status agf2_compress(agf2_handle_t hh, int nphys, const double* m0, const d
     AGF2_REQUIRE(m0 && m1 && naux_out && e_aux && v_aux, "NULL argument");
     AGF2_REQUIRE(tol >= 0.0 && tol < 1.0, "tol must be in [0, 1)");
     *naux_out = 0;
+    const long nn = (long)nphys * nphys;
+    FiniteCheck(h).add(m0, nn, "m0").add(m1, nn, "m1").run();
     *naux_out = compress_impl(h, nphys, m0, m1, tol, e_aux, v_aux);
   });
 }
@@ -937,6 +992,14 @@ agf2_status agf2_fock_loop(agf2_handle_t hh, int nphys, int naux, const double* 
     AGF2_REQUIRE(Lpq && hcore && rdm1 && fock && e_pole && u_pole && nocc_pole && mu &&
                      shift && n_cycle && (naux_se == 0 || (e_se && v_se)),
                  "NULL argument");
+    const long nn = (long)nphys * nphys;
+    FiniteCheck(h)
+        .add(Lpq, naux * nn, "Lpq")
+        .add(hcore, nn, "hcore")
+        .add(rdm1, nn, "rdm1")
+        .add(e_se, naux_se, "e_se")
+        .add(v_se, (long)nphys * naux_se, "v_se")
+        .run();
     agf2_fock_opts o;
     agf2_fock_opts_default(&o);
     if (opts) o = *opts;
@@ -968,6 +1031,18 @@ agf2_status agf2_energy_gf(agf2_handle_t hh, int nphys, const double* hcore, con
     AGF2_REQUIRE((naux_occ == 0 || (e_se_occ && v_se_occ)) &&
                      (naux_vir == 0 || (e_se_vir && v_se_vir)),
                  "NULL auxiliary argument");
+    const long nn = (long)nphys * nphys;
+    FiniteCheck(h)
+        .add(hcore, nn, "hcore")
+        .add(fock, nn, "fock")
+        .add(rdm1, nn, "rdm1")
+        .add(e_pole, npole, "e_pole")
+        .add(u_pole, (long)nphys * npole, "u_pole")
+        .add(e_se_occ, naux_occ, "e_se_occ")
+        .add(v_se_occ, (long)nphys * naux_occ, "v_se_occ")
+        .add(e_se_vir, naux_vir, "e_se_vir")
+        .add(v_se_vir, (long)nphys * naux_vir, "v_se_vir")
+        .run();
     energy_impl(h, nphys, hcore, fock, rdm1, npole, nocc_pole, e_pole, u_pole, naux_occ,
                 e_se_occ, v_se_occ, naux_vir, e_se_vir, v_se_vir, e_1b, e_2b);
   });
@@ -981,6 +1056,12 @@ agf2_status agf2_spectral_function(agf2_handle_t hh, int nphys, int npole,
     AGF2_REQUIRE(nphys >= 1 && npole >= 1 && nomega >= 0, "bad sizes");
     AGF2_REQUIRE(eta > 0.0 && std::isfinite(eta), "eta must be positive");
     AGF2_REQUIRE(e_pole && u_pole && (nomega == 0 || (omega && A)), "NULL argument");
+    FiniteCheck(h)
+        .add(e_pole, npole, "e_pole")
+        .add(u_pole, (long)nphys * npole, "u_pole")
+        .add(weight, nphys, "weight")
+        .add(omega, nomega, "omega")
+        .run();
     spectral_function(h, nphys, npole, e_pole, u_pole, weight, nomega, omega, eta, A);
   });
 }

@@ -151,6 +151,20 @@ void axpby_f64(long n, double a, const double* x, double b, double* y,
                hipStream_t s);
 void symmetrize_f64(int N, double* A, hipStream_t s);
 
+// Non-finite input check: each array added is scanned on the device (one
+// launch per array, one host synchronisation in run()); run() throws
+// AGF2_ERR_ARG naming the first array that holds a NaN or an infinity.
+// Arrays of length 0 or NULL pointers are skipped; at most 32 per check.
+struct FiniteCheck {
+  Handle& h;
+  std::vector<const double*> ptr;
+  std::vector<long> len;
+  std::vector<std::string> name;
+  explicit FiniteCheck(Handle& hh) : h(hh) {}
+  FiniteCheck& add(const double* p, long n, const char* what);
+  void run();
+};
+
 // Per-kernel-class timing: hipEvents recorded on the handle's stream around
 // each launch of a class, with the launch's algorithmic flop and byte counts.
 struct ProfRecord {
@@ -211,6 +225,7 @@ struct Handle {
   DevBuf ws_mlp[2];   // warm-start loss partials and prediction scratch
   DevBuf ws_spec;     // spectral function: pole weights
   DevBuf ws_red;
+  DevBuf ws_check;    // flags of the non-finite input check
   double* host_red = nullptr;   // pinned scratch for small reductions
   size_t host_red_n = 0;
   ~Handle();

@@ -4,8 +4,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <exception>
 #include <new>
+#include <string>
 
 #include "agf2_internal.h"
 
@@ -133,33 +135,64 @@ struct MomentDiis {
     for (int a = 0; a < n; ++a)
       axpby_f64(len, rhs[a], store + (long)order[a] * 2 * len, a == 0 ? 0.0 : 1.0, x, h.stream);
   }
+  // History to / from a host blob: prev [len], store [max(space,1)][2][len],
+  // B [max(space,1)^2]; the blob pointer advances past what was written/read.
+  void save(double*& d, hipStream_t st) const {
+    const int sp = std::max(space, 1);
+    AGF2_HIP(hipMemcpyAsync(d, prev, len * sizeof(double), hipMemcpyDeviceToHost, st));
+    d += len;
+    AGF2_HIP(hipMemcpyAsync(d, store, (long)sp * 2 * len * sizeof(double), hipMemcpyDeviceToHost,
+                            st));
+    d += (long)sp * 2 * len;
+    for (size_t k = 0; k < B.size(); ++k) d[k] = B[k];
+    d += B.size();
+  }
+  void restore(bool have, const int* ord, int n, const double* d) {
+    const int sp = std::max(space, 1);
+    have_prev = have;
+    order.assign(ord, ord + n);
+    for (int k : order)
+      if (k < 0 || k >= space) throw Error{AGF2_ERR_ARG, "state_in is inconsistent"};
+    AGF2_HIP(hipMemcpyAsync(prev, d, len * sizeof(double), hipMemcpyHostToDevice, h.stream));
+    d += len;
+    AGF2_HIP(hipMemcpyAsync(store, d, (long)sp * 2 * len * sizeof(double),
+                            hipMemcpyHostToDevice, h.stream));
+    d += (long)sp * 2 * len;
+    for (size_t k = 0; k < B.size(); ++k) B[k] = d[k];
+  }
 };
 
 }  // namespace agf2
 
-using namespace agf2;
+namespace agf2 {
+namespace {
 
-extern "C" {
+// Saved state of agf2_run between iterations (host blob, see
+// agf2_run_state_bytes): a fixed header, then the device arrays in order.
+struct RunStateHeader {
+  char magic[8];          // "AGF2RUN1"
+  int nphys, diis_space;
+  int next_iter;          // index of the next iteration to run
+  int npole, nocc_pole;
+  int have_prev;          // a previous iteration's E, IP, EA exist
+  int diis_have_prev, diis_n;
+  int diis_order[64];     // slots, oldest first
+  double prev_e, prev_ip, prev_ea;
+};
 
-void agf2_run_opts_default(agf2_run_opts* o) {
-  if (!o) return;
-  o->max_iter = 20;
-  o->conv_tol = 1e-8;
-  o->conv_tol_ipea = 1e-7;
-  o->diis_space = 8;
-  o->damping = 0.0;
-  o->prec = AGF2_FP64;
-  o->compress_tol = 0.0;
-  agf2_fock_opts_default(&o->fock);
+long state_doubles(int N, int space) {
+  const long nn = (long)N * N;
+  return 3L * N + 3L * N * N + nn + 4 * nn + 4 * nn + (long)std::max(space, 1) * 2 * 4 * nn +
+         (long)std::max(space, 1) * std::max(space, 1);
 }
 
-agf2_status agf2_run(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int naux,
-                     const double* Lpq, const double* hcore, const double* e_mf, int nocc,
-                     const double* dm_init, agf2_iter_record* records, int* n_records,
-                     int* converged, double* e_pole, double* u_pole, int* nocc_pole,
-                     double* rdm1) {
-  if (!hh) return AGF2_ERR_ARG;
-  Handle& h = *reinterpret_cast<Handle*>(hh);
+}  // namespace
+
+agf2_status run_impl(Handle& h, const agf2_run_opts* opts, int nphys, int naux, const double* Lpq,
+                     const double* hcore, const double* e_mf, int nocc, const double* dm_init,
+                     const void* state_in, void* state_out, int max_iter_call,
+                     agf2_iter_record* records, int* n_records, int* converged, double* e_pole,
+                     double* u_pole, int* nocc_pole, double* rdm1) {
   agf2_status result = AGF2_OK;
   try {
     int prev_dev = 0;
@@ -176,12 +209,19 @@ agf2_status agf2_run(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int
     AGF2_REQUIRE(Lpq && hcore && e_mf && records && n_records && converged && e_pole && u_pole &&
                      nocc_pole && rdm1,
                  "NULL argument");
-    AGF2_REQUIRE(o.max_iter >= 0 && o.diis_space >= 0 && o.damping >= 0.0 && o.damping < 1.0,
+    AGF2_REQUIRE(o.max_iter >= 0 && o.diis_space >= 0 && o.diis_space <= 64 &&
+                     o.damping >= 0.0 && o.damping < 1.0,
                  "bad run options");
     hipStream_t st = h.stream;
     const int N = nphys;
     const long nn = (long)N * N;
     const int nmax = 3 * N;
+    FiniteCheck(h)
+        .add(Lpq, (long)naux * nn, "Lpq")
+        .add(hcore, nn, "hcore")
+        .add(e_mf, N, "e_mf")
+        .add(dm_init, 4 * nn, "dm_init")
+        .run();
     // state
     double* w = h.ws_run[0].as<double>(2L * nmax + 2L * N * nmax + nn + 8);
     double* e_cur = w;
@@ -201,15 +241,50 @@ agf2_status agf2_run(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int
     double* fock = v_se + 2 * nn;
     double* vo_p = h.ws_run[3].as<double>(2 * nn);
     double* vv_p = vo_p + nn;
-    hipLaunchKernelGGL(init_reference, dim3(nblk(nn)), dim3(256), 0, st, N, nocc, e_mf, e_cur,
-                       u_cur, rdm1);
-    AGF2_CHECK_LAUNCH();
     int npole = N, nocc_p = nocc;
     MomentDiis diis(h, 4 * nn, o.diis_space);
-    bool conv = false, have_prev = false;
+    bool conv = false, have_prev = false, fock_failed = false;
     double prev_e = 0, prev_ip = 0, prev_ea = 0;
+    int it0 = 0;
+    if (state_in) {
+      RunStateHeader hd;
+      std::memcpy(&hd, state_in, sizeof hd);
+      AGF2_REQUIRE(std::memcmp(hd.magic, "AGF2RUN1", 8) == 0, "state_in is not an agf2_run state");
+      AGF2_REQUIRE(hd.nphys == N && hd.diis_space == o.diis_space,
+                   "state_in was saved for another nphys or diis_space");
+      AGF2_REQUIRE(hd.npole >= 2 && hd.npole <= nmax && hd.nocc_pole >= 1 &&
+                       hd.nocc_pole < hd.npole && hd.next_iter >= 1 &&
+                       hd.diis_n >= 0 && hd.diis_n <= o.diis_space,
+                   "state_in is inconsistent");
+      const double* d = reinterpret_cast<const double*>(static_cast<const char*>(state_in) +
+                                                         sizeof hd);
+      it0 = hd.next_iter;
+      npole = hd.npole;
+      nocc_p = hd.nocc_pole;
+      have_prev = hd.have_prev != 0;
+      prev_e = hd.prev_e;
+      prev_ip = hd.prev_ip;
+      prev_ea = hd.prev_ea;
+      auto up = [&](double* dst, long n) {
+        AGF2_HIP(hipMemcpyAsync(dst, d, n * sizeof(double), hipMemcpyHostToDevice, st));
+        d += n;
+      };
+      up(e_cur, nmax);
+      up(u_cur, (long)N * nmax);
+      up(rdm1, nn);
+      up(mprev, 4 * nn);
+      diis.restore(hd.diis_have_prev != 0, hd.diis_order, hd.diis_n, d);
+      AGF2_HIP(hipStreamSynchronize(st));
+    } else {
+      hipLaunchKernelGGL(init_reference, dim3(nblk(nn)), dim3(256), 0, st, N, nocc, e_mf, e_cur,
+                         u_cur, rdm1);
+      AGF2_CHECK_LAUNCH();
+    }
     int nrec = 0;
-    for (int it = 0; it <= o.max_iter; ++it) {
+    int it_end = o.max_iter;
+    if (max_iter_call > 0) it_end = std::min(it_end, it0 + max_iter_call - 1);
+    int it = it0;
+    for (; it <= it_end; ++it) {
       agf2_iter_record rec{};
       rec.iter = it;
       double t0 = now();
@@ -283,6 +358,7 @@ agf2_status agf2_run(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int
       rec.nocc_pole = fl.nocc_pole;
       rec.npole = npole_new;
       rec.fock_cycles = fl.n_cycle;
+      rec.fock_converged = fl.converged ? 1 : 0;
       rec.e_1b = e1;
       rec.e_2b = e2;
       rec.e_tot = e1 + e2;
@@ -298,9 +374,17 @@ agf2_status agf2_run(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int
       std::swap(u_cur, u_new);
       npole = npole_new;
       nocc_p = fl.nocc_pole;
+      if (!fl.converged) {
+        // the density of this iteration is not relaxed: stop here, with the
+        // outputs holding this iteration's Green's function and density
+        fock_failed = true;
+        ++it;
+        break;
+      }
       if (have_prev && std::fabs(rec.e_tot - prev_e) < o.conv_tol &&
           std::max(std::fabs(rec.ip - prev_ip), std::fabs(rec.ea - prev_ea)) < o.conv_tol_ipea) {
         conv = true;
+        ++it;
         break;
       }
       have_prev = true;
@@ -313,12 +397,44 @@ agf2_status agf2_run(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int
     AGF2_HIP(hipMemcpyAsync(e_pole, e_cur, npole * sizeof(double), hipMemcpyDeviceToDevice, st));
     AGF2_HIP(hipMemcpyAsync(u_pole, u_cur, (long)N * npole * sizeof(double),
                             hipMemcpyDeviceToDevice, st));
+    if (state_out) {
+      RunStateHeader hd;
+      std::memset(&hd, 0, sizeof hd);
+      std::memcpy(hd.magic, "AGF2RUN1", 8);
+      hd.nphys = N;
+      hd.diis_space = o.diis_space;
+      hd.next_iter = it;
+      hd.npole = npole;
+      hd.nocc_pole = nocc_p;
+      hd.have_prev = have_prev ? 1 : 0;
+      hd.prev_e = prev_e;
+      hd.prev_ip = prev_ip;
+      hd.prev_ea = prev_ea;
+      hd.diis_have_prev = diis.have_prev ? 1 : 0;
+      hd.diis_n = (int)diis.order.size();
+      for (int k = 0; k < hd.diis_n; ++k) hd.diis_order[k] = diis.order[k];
+      std::memcpy(state_out, &hd, sizeof hd);
+      double* d = reinterpret_cast<double*>(static_cast<char*>(state_out) + sizeof hd);
+      auto down = [&](const double* src, long n) {
+        AGF2_HIP(hipMemcpyAsync(d, src, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        d += n;
+      };
+      down(e_cur, nmax);
+      down(u_cur, (long)N * nmax);
+      down(rdm1, nn);
+      down(mprev, 4 * nn);
+      diis.save(d, st);
+    }
     AGF2_HIP(hipStreamSynchronize(st));
     *nocc_pole = nocc_p;
     *n_records = nrec;
     *converged = conv ? 1 : 0;
     h.last_error.clear();
-    if (!conv) {
+    if (fock_failed) {
+      h.last_error = "the Fock loop reached max_cycle at iteration " +
+                     std::to_string(records[nrec - 1].iter);
+      result = AGF2_ERR_NO_CONVERGE;
+    } else if (!conv && it > o.max_iter) {
       h.last_error = "AGF2 reached max_iter without converging";
       result = AGF2_ERR_NO_CONVERGE;
     }
@@ -333,6 +449,52 @@ agf2_status agf2_run(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int
     result = AGF2_ERR_HIP;
   }
   return result;
+}
+
+}  // namespace agf2
+
+using namespace agf2;
+
+extern "C" {
+
+void agf2_run_opts_default(agf2_run_opts* o) {
+  if (!o) return;
+  o->max_iter = 20;
+  o->conv_tol = 1e-8;
+  o->conv_tol_ipea = 1e-7;
+  o->diis_space = 8;
+  o->damping = 0.0;
+  o->prec = AGF2_FP64;
+  o->compress_tol = 0.0;
+  agf2_fock_opts_default(&o->fock);
+}
+
+long agf2_run_state_bytes(int nphys, int diis_space) {
+  if (nphys < 1 || diis_space < 0 || diis_space > 64) return -1;
+  return (long)sizeof(RunStateHeader) + 8L * state_doubles(nphys, diis_space);
+}
+
+agf2_status agf2_run(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int naux,
+                     const double* Lpq, const double* hcore, const double* e_mf, int nocc,
+                     const double* dm_init, agf2_iter_record* records, int* n_records,
+                     int* converged, double* e_pole, double* u_pole, int* nocc_pole,
+                     double* rdm1) {
+  if (!hh) return AGF2_ERR_ARG;
+  return run_impl(*reinterpret_cast<Handle*>(hh), opts, nphys, naux, Lpq, hcore, e_mf, nocc,
+                  dm_init, nullptr, nullptr, 0, records, n_records, converged, e_pole, u_pole,
+                  nocc_pole, rdm1);
+}
+
+agf2_status agf2_run_resume(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int naux,
+                            const double* Lpq, const double* hcore, const double* e_mf,
+                            int nocc, const double* dm_init, const void* state_in,
+                            void* state_out, int max_iter_call, agf2_iter_record* records,
+                            int* n_records, int* converged, double* e_pole, double* u_pole,
+                            int* nocc_pole, double* rdm1) {
+  if (!hh) return AGF2_ERR_ARG;
+  return run_impl(*reinterpret_cast<Handle*>(hh), opts, nphys, naux, Lpq, hcore, e_mf, nocc,
+                  dm_init, state_in, state_out, max_iter_call, records, n_records, converged,
+                  e_pole, u_pole, nocc_pole, rdm1);
 }
 
 }  // extern "C"

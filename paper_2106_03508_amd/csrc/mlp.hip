@@ -546,6 +546,7 @@ agf2_status agf2_mlp_features(agf2_handle_t hh, int nphys, int nocc, const doubl
   return guarded(hh, [&](Handle& h) {
     AGF2_REQUIRE(nphys >= 2 && nocc >= 1 && nocc < nphys, "need 1 <= nocc < nphys");
     AGF2_REQUIRE(e_mf && m0 && X && scale, "NULL pointer");
+    FiniteCheck(h).add(e_mf, nphys, "e_mf").add(m0, 4L * nphys * nphys, "m0").run();
     hipLaunchKernelGGL(features_kernel, dim3(1), dim3(256), 0, h.stream, nphys, nocc, e_mf, m0, X,
                        scale);
     AGF2_CHECK_LAUNCH();
@@ -566,6 +567,11 @@ agf2_status agf2_mlp_loss_grad(agf2_handle_t hh, int nphys, const float* Y, cons
   return guarded(hh, [&](Handle& h) {
     AGF2_REQUIRE(nphys >= 1 && nphys <= 65535, "bad nphys");
     AGF2_REQUIRE(Y && m0 && mconv && scale && dY && loss, "NULL pointer");
+    FiniteCheck(h)
+        .add(m0, 4L * nphys * nphys, "m0")
+        .add(mconv, 4L * nphys * nphys, "mconv")
+        .add(scale, 4, "scale")
+        .run();
     double* lpart = h.ws_mlp[0].as<double>(4L * nphys);
     hipLaunchKernelGGL(head_loss, dim3(nphys, NMOM), dim3(256), 0, h.stream, nphys, Y, m0, mconv,
                        scale, dY, lpart);
@@ -608,6 +614,7 @@ agf2_status agf2_mlp_predict_correction(agf2_handle_t hh, agf2_mlp_t p, int nphy
     agf2_mlp_s& net = net_of(p, h);
     AGF2_REQUIRE(nphys >= 2 && nocc >= 1 && nocc < nphys, "need 1 <= nocc < nphys");
     AGF2_REQUIRE(e_mf && m0 && dm, "NULL pointer");
+    FiniteCheck(h).add(e_mf, nphys, "e_mf").add(m0, 4L * nphys * nphys, "m0").run();
     char* ws = static_cast<char*>(h.ws_mlp[1].get((long)nphys * (NF + NO) * 4 + 512));
     float* X = reinterpret_cast<float*>(ws);
     float* Y = X + (long)nphys * NF;

@@ -449,6 +449,18 @@ extern "C" agf2_status agf2_build_moments_batched(agf2_handle_t hh, int nsys,
       key.push_back(SysKey{y.nphys, y.naux, y.npole, y.nocc_pole, y.Lpq, y.e_pole, y.u_pole,
                            y.m0_occ, y.m1_occ, y.m0_vir, y.m1_vir});
     }
+    // non-finite inputs are rejected on every call (the graph replays the
+    // arrays' current values)
+    for (int s0 = 0; s0 < nsys; s0 += 10) {
+      FiniteCheck chk(h);
+      for (int s = s0; s < std::min(nsys, s0 + 10); ++s) {
+        const agf2_system& y = sys[s];
+        chk.add(y.Lpq, (long)y.naux * y.nphys * y.nphys, "Lpq of a batched system")
+            .add(y.e_pole, y.npole, "e_pole of a batched system")
+            .add(y.u_pole, (long)y.nphys * y.npole, "u_pole of a batched system");
+      }
+      chk.run();
+    }
     if (!h.batch || !(h.batch->key == key)) {
       destroy_batch_plan(h.batch);
       h.batch = nullptr;

@@ -47,3 +47,17 @@ def test_null_handle_is_rejected(lib):
     assert b"NULL" in lib.agf2_last_error(None)
     lib.agf2_destroy.argtypes = [ctypes.c_void_p]
     assert lib.agf2_destroy(None) == -1
+
+
+def test_run_state_size(lib):
+    """The checkpoint size of agf2_run is a host-side formula: header plus
+    the saved arrays (poles, density, previous moments, DIIS history)."""
+    lib.agf2_run_state_bytes.restype = ctypes.c_long
+    lib.agf2_run_state_bytes.argtypes = [ctypes.c_int, ctypes.c_int]
+    n, sp = 24, 8
+    nn = n * n
+    doubles = 3 * n + 3 * nn + nn + 4 * nn + 4 * nn + sp * 2 * 4 * nn + sp * sp
+    b = lib.agf2_run_state_bytes(n, sp)
+    assert 0 < b - 8 * doubles <= 512
+    assert lib.agf2_run_state_bytes(0, 8) == -1
+    assert lib.agf2_run_state_bytes(10, 65) == -1

@@ -175,8 +175,11 @@ def _iteration0_inputs(seed=0, nmo=24, nocc=5, naux=80):
 
 
 def test_fock_loop_matches_oracle(h):
-    """Same self-energy into both Fock loops. The shift fit stops at
-    |count - nelec| < 1e-10, so poles agree to ~1e-9."""
+    """Same self-energy into both Fock loops, compared on the converged
+    result. The oracle fits the shift by bisection in every cycle, the
+    library by Newton and first-order steps; both stop when the density
+    changes by less than 1e-8 and return a density whose count is fitted to
+    1e-10, so the fixed points agree to ~1e-9."""
     from paper_2106_03508_amd import agf2
     eps, L, hc, nocc, eo, vo, ev, vv = _iteration0_inputs()
     e_aux = np.concatenate([eo, ev]); v_aux = np.hstack([vo, vv])

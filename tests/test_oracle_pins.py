@@ -293,15 +293,30 @@ def test_electron_count_monotone_in_shift():
     assert np.all(np.diff(cs) >= -1e-12)
 
 
-def test_shift_derivative_matches_finite_differences():
-    """The first-order response of the density and of the electron count to
-    the auxiliary shift, against central differences of the exact
-    eigendecomposition at a fixed number of occupied poles."""
+def _shift_derivative(lam, u, n):
+    """The library's reading of the count derivative (first-order
+    perturbation of the eigenvectors in the common auxiliary shift, which
+    enters the extended Hamiltonian as Delta times the projector onto the
+    auxiliary space): with C_o, C_v the physical parts of the occupied and
+    virtual eigenvectors, P = C_o^T C_v and M_ij = P_ij / (lam_j - lam_i),
+    dD/dDelta = 2 (C_o M C_v^T + C_v M^T C_o^T) and dN/dDelta = 4 sum M.P.
+    A test helper only: the oracle's Fock loop fits the shift by bisection."""
+    Co, Cv = u[:, :n], u[:, n:]
+    P = Co.T @ Cv
+    M = P / (lam[None, n:] - lam[:n, None])
+    G = Co @ M @ Cv.T
+    return 4.0 * np.sum(M * P), 2.0 * (G + G.T)
+
+
+def test_library_shift_derivative_matches_finite_differences():
+    """The count derivative the GPU Fock loop takes its Newton steps with,
+    against central differences of the oracle's exact eigendecomposition at a
+    fixed number of occupied poles."""
     eps, L, nocc, h, (eo, vo, ev, vv), fl = _iteration0()
     e_aux = np.concatenate([eo, ev]); v_aux = np.hstack([vo, vv])
     F, d0 = fl["fock"], fl["shift"] + 0.013
     lam, u, n, cnt, mu = O._solve(F, e_aux, v_aux, d0, 2 * nocc)
-    dN, dD = O.shift_derivative(lam, u, n)
+    dN, dD = _shift_derivative(lam, u, n)
 
     def dens(d):
         _, ud, *_ = O._solve(F, e_aux, v_aux, d, 2 * nocc)
@@ -320,19 +335,39 @@ def test_shift_derivative_matches_finite_differences():
     assert abs(c1 - 2 * nocc) < 1e-2 * abs(g0)
 
 
-def test_fock_loop_first_order_steps_keep_the_solution():
-    """The first-order shift steps change the path, not the converged loop:
-    the same result with them switched off (every cycle refitted)."""
+def test_fock_loop_fit_settings_keep_the_solution():
+    """The bracket step and a tighter count tolerance change the path of the
+    shift fit, not the converged loop; every cycle's count meets the fit
+    tolerance (the returned count too)."""
     eps, L, nocc, h, (eo, vo, ev, vv), fl = _iteration0()
     e_aux = np.concatenate([eo, ev]); v_aux = np.hstack([vo, vv])
     ref = O.fock_loop(h, L, 2 * nocc, e_aux, v_aux, O.reference_density(eps.shape[0], nocc),
-                      newton_max=0.0)
+                      tol_nelec=1e-12, step0=0.1)
     assert fl["converged"] and ref["converged"]
     assert fl["nocc_pole"] == ref["nocc_pole"]
+    assert abs(fl["nelec"] - 2 * nocc) < 1e-10 and abs(ref["nelec"] - 2 * nocc) < 1e-12
     assert abs(fl["shift"] - ref["shift"]) < 1e-8
     assert np.abs(fl["rdm1"] - ref["rdm1"]).max() < 1e-8
     assert np.abs(fl["e_pole"] - ref["e_pole"]).max() < 1e-8
-    assert fl["n_eig"] < ref["n_eig"]
+
+
+def test_fock_loop_cycle_limit_returns_a_consistent_iterate():
+    """At the cycle limit the loop reports no convergence and returns the
+    poles of its last Fock matrix at a shift fitted there: exact eigenpairs of
+    that extended Hamiltonian, the right electron count, and the density of
+    those poles."""
+    eps, L, nocc, h, (eo, vo, ev, vv), fl = _iteration0()
+    e_aux = np.concatenate([eo, ev]); v_aux = np.hstack([vo, vv])
+    N = eps.shape[0]
+    r = O.fock_loop(h, L, 2 * nocc, e_aux, v_aux, O.reference_density(N, nocc), max_cycle=1)
+    assert not r["converged"] and r["n_cycle"] == 1
+    H = O.extended_hamiltonian(r["fock"], e_aux + r["shift"], v_aux)
+    assert np.allclose(np.linalg.eigvalsh(H), r["e_pole"], atol=1e-12)
+    u, n = r["u_pole"], r["nocc_pole"]
+    assert abs(2 * np.sum(u[:, :n] ** 2) - 2 * nocc) < 1e-10
+    assert np.abs(r["rdm1"] - 2 * u[:, :n] @ u[:, :n].T).max() < 1e-14
+    # the last Fock matrix is that of the first cycle's density, not the input's
+    assert np.abs(r["fock"] - O.fock_matrix(h, L, O.reference_density(N, nocc))).max() > 1e-6
 
 
 def test_energy_two_sided_equals_direct_form():
