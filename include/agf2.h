@@ -26,7 +26,8 @@
  *     before use; a NaN or an infinity in any of them returns AGF2_ERR_ARG
  *     (the message names the array) and nothing is computed. The scan reads
  *     each input once (about 6 ms for a 28 GB DF tensor). float32 arrays of
- *     the warm-start network's calls are not scanned.
+ *     the warm-start network's calls and the inputs of the allocation-free
+ *     agf2_spectral_function_noalloc are not scanned.
  *   - A handle must not be used by two threads at once. It owns a device
  *     workspace that grows on demand and is freed by agf2_destroy().
  *
@@ -250,6 +251,28 @@ agf2_status agf2_spectral_function(agf2_handle_t handle, int nphys, int npole,
                                    const double* e_pole, const double* u_pole,
                                    const double* weight, int nomega,
                                    const double* omega, double eta, double* A);
+
+/*
+ * Allocation-free variant of agf2_spectral_function, for callers that
+ * cannot allocate device memory during the call: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation. Same
+ * arguments, result and kernels as agf2_spectral_function, but its partial
+ * sums live in a static device array of the library (one per GPU, 4.25 MiB,
+ * kept until the process ends; its address is resolved by agf2_create), so
+ * the call allocates nothing, records no event, does not scan its inputs for
+ * non-finite values and does not synchronise. Every call on one GPU shares
+ * that array, which keeps the last call's contents (each call overwrites all
+ * it reads): calls that overlap on one GPU (several streams or threads)
+ * race. Errors: AGF2_ERR_ARG for npole > AGF2_SPECTRUM_NOALLOC_MAX_POLE and
+ * the argument errors of agf2_spectral_function.
+ */
+#define AGF2_SPECTRUM_NOALLOC_MAX_POLE 32768
+agf2_status agf2_spectral_function_noalloc(agf2_handle_t handle, int nphys,
+                                           int npole, const double* e_pole,
+                                           const double* u_pole,
+                                           const double* weight, int nomega,
+                                           const double* omega, double eta,
+                                           double* A);
 
 /* One system of a batched moment build (all pointers device, row-major,
  * float64; meaning as in agf2_build_moments). */

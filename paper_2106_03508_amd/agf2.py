@@ -71,6 +71,7 @@ SIGNATURES = {
     "agf2_energy_gf": (_I, [_P, _I, _P, _P, _P, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P,
                             _DP, _DP]),
     "agf2_spectral_function": (_I, [_P, _I, _I, _P, _P, _P, _I, _P, _D, _P]),
+    "agf2_spectral_function_noalloc": (_I, [_P, _I, _I, _P, _P, _P, _I, _P, _D, _P]),
     "agf2_run_opts_default": (None, [ctypes.POINTER(RunOpts)]),
     "agf2_run": (_I, [_P, ctypes.POINTER(RunOpts), _I, _I, _P, _P, _P, _I, _P,
                       ctypes.POINTER(IterRecord), _IP, _IP, _P, _P, _IP, _P]),

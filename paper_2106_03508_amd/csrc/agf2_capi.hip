@@ -875,6 +875,14 @@ agf2_status agf2_create(agf2_handle_t* out, int device, void* stream) {
   if (st == AGF2_OK && hipHostMalloc(reinterpret_cast<void**>(&h->host_red), 4096 * sizeof(double)) != hipSuccess)
     st = AGF2_ERR_HIP;
   else if (st == AGF2_OK) h->host_red_n = 4096;
+  if (st == AGF2_OK) {
+    // the device address of the allocation-free spectral function's scratch
+    try {
+      (void)noalloc_scratch(device);
+    } catch (const Error&) {
+      st = AGF2_ERR_HIP;
+    }
+  }
   (void)hipSetDevice(prev);
   if (st != AGF2_OK) { delete h; return st; }
   *out = reinterpret_cast<agf2_handle_t>(h);
@@ -1063,6 +1071,18 @@ agf2_status agf2_spectral_function(agf2_handle_t hh, int nphys, int npole,
         .add(omega, nomega, "omega")
         .run();
     spectral_function(h, nphys, npole, e_pole, u_pole, weight, nomega, omega, eta, A);
+  });
+}
+
+agf2_status agf2_spectral_function_noalloc(agf2_handle_t hh, int nphys, int npole,
+                                           const double* e_pole, const double* u_pole,
+                                           const double* weight, int nomega,
+                                           const double* omega, double eta, double* A) {
+  return guarded(hh, [&](Handle& h) {
+    AGF2_REQUIRE(nphys >= 1 && npole >= 1 && nomega >= 0, "bad sizes");
+    AGF2_REQUIRE(eta > 0.0 && std::isfinite(eta), "eta must be positive");
+    AGF2_REQUIRE(e_pole && u_pole && (nomega == 0 || (omega && A)), "NULL argument");
+    spectral_function_noalloc(h, nphys, npole, e_pole, u_pole, weight, nomega, omega, eta, A);
   });
 }
 

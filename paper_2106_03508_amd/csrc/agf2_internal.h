@@ -202,6 +202,13 @@ void build_moments(Handle& h, agf2_precision prec, int N, int Q, const double* L
 void spectral_function(Handle& h, int nphys, int npole, const double* e_pole,
                        const double* u_pole, const double* weight, int nomega,
                        const double* omega, double eta, double* A);
+// The allocation-free variant over the device's static scratch array, and
+// the per-device address of that array (resolved at the first call for a
+// device, which agf2_create makes).
+void spectral_function_noalloc(Handle& h, int nphys, int npole, const double* e_pole,
+                               const double* u_pole, const double* weight, int nomega,
+                               const double* omega, double eta, double* A);
+double* noalloc_scratch(int device);
 
 struct BatchPlan;   // batched moment build (moments_batched.hip)
 void destroy_batch_plan(BatchPlan* p);

@@ -7,6 +7,7 @@
 // whose eigenpairs are the poles (lam_l, u[:, l]).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "agf2_internal.h"
 
@@ -17,6 +18,18 @@ namespace {
 constexpr int ST = 256;
 
 constexpr int PS = 16;   // row ranges of the pole-weight sums
+
+// Device scratch of the allocation-free entry point: the PS partial
+// pole-weight rows and the summed weights, [(PS + 1) * kNoallocMaxPole]
+// doubles (4.25 MiB), one copy per GPU for the life of the process. Host code
+// must not use the name of this array as an address: it takes the per-device
+// address that hipGetSymbolAddress returns (noalloc_scratch below).
+constexpr int kNoallocMaxPole = AGF2_SPECTRUM_NOALLOC_MAX_POLE;
+static __device__ __align__(256) double scratch[(PS + 1) * kNoallocMaxPole];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
 
 // part[y][l] = sum over rows p of range y of P_p u[p][l]^2 (P = 1 when weight
 // is NULL); threads over poles, so each read of a row of u is contiguous
@@ -68,14 +81,12 @@ __global__ __launch_bounds__(ST) void spectral_kernel(int npole, const double* l
 
 }  // namespace
 
-void spectral_function(Handle& h, int nphys, int npole, const double* e_pole,
-                       const double* u_pole, const double* weight, int nomega,
-                       const double* omega, double eta, double* A) {
-  if (nomega == 0) return;
-  hipStream_t st = h.stream;
-  ProfScope ps(h, "spectrum", 3.0 * nphys * (double)npole + 5.0 * nomega * (double)npole,
-               8.0 * ((double)nphys * npole + 2.0 * npole + 2.0 * nomega));
-  double* part = h.ws_spec.as<double>((long)(PS + 1) * npole);
+namespace {
+
+// the three launches over a caller-provided scratch of (PS + 1) * npole doubles
+void spectral_launch(hipStream_t st, int nphys, int npole, const double* e_pole,
+                     const double* u_pole, const double* weight, int nomega,
+                     const double* omega, double eta, double* A, double* part) {
   double* w = part + (long)PS * npole;
   const int gl = (npole + ST - 1) / ST;
   hipLaunchKernelGGL(pole_weight_kernel, dim3(gl, PS), dim3(ST), 0, st, nphys, npole, u_pole,
@@ -87,6 +98,49 @@ void spectral_function(Handle& h, int nphys, int npole, const double* e_pole,
   hipLaunchKernelGGL(spectral_kernel, dim3((nomega + per - 1) / per), dim3(ST), 0, st, npole,
                      e_pole, w, nomega, omega, eta, A);
   AGF2_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+void spectral_function(Handle& h, int nphys, int npole, const double* e_pole,
+                       const double* u_pole, const double* weight, int nomega,
+                       const double* omega, double eta, double* A) {
+  if (nomega == 0) return;
+  ProfScope ps(h, "spectrum", 3.0 * nphys * (double)npole + 5.0 * nomega * (double)npole,
+               8.0 * ((double)nphys * npole + 2.0 * npole + 2.0 * nomega));
+  double* part = h.ws_spec.as<double>((long)(PS + 1) * npole);
+  spectral_launch(h.stream, nphys, npole, e_pole, u_pole, weight, nomega, omega, eta, A, part);
+}
+
+// Device address of this GPU's scratch array: resolved once per device with
+// that device current (the handle's set-up calls this), then cached.
+double* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    throw Error{AGF2_ERR_ARG, "device index beyond the scratch table"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    DeviceGuard g(device);
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error{AGF2_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                    hipGetErrorString(e)};
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[device];
+}
+
+// The same launches on the device's scratch array: no allocation, no event,
+// no host synchronisation.
+void spectral_function_noalloc(Handle& h, int nphys, int npole, const double* e_pole,
+                               const double* u_pole, const double* weight, int nomega,
+                               const double* omega, double eta, double* A) {
+  if (npole > kNoallocMaxPole)
+    throw Error{AGF2_ERR_ARG, "npole exceeds AGF2_SPECTRUM_NOALLOC_MAX_POLE (" +
+                                  std::to_string(kNoallocMaxPole) + ")"};
+  if (nomega == 0) return;
+  spectral_launch(h.stream, nphys, npole, e_pole, u_pole, weight, nomega, omega, eta, A,
+                  noalloc_scratch(h.device));
 }
 
 }  // namespace agf2
