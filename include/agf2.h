@@ -114,6 +114,52 @@ agf2_status agf2_build_moments(agf2_handle_t handle, agf2_precision prec,
                                double* m1_occ, double* m0_vir, double* m1_vir);
 
 /*
+ * Moments 0 .. nmom-1 of the lesser and greater self-energy: the same sums
+ * as agf2_build_moments, the n-th moment carrying the n-th power of the
+ * weight, (e_i + e_j - e_a)^n resp. (e_a + e_b - e_i)^n. Moments 0 .. 2k+1
+ * are what a compression to k + 1 Lanczos blocks conserves (the other
+ * truncations of the AGF2(n,m) family that the compression section names).
+ *   nmom       even, 2 <= nmom <= 16; above 2 only prec = AGF2_FP64.
+ *   m_occ, m_vir  device [nmom][nphys][nphys] outputs (moment n at offset
+ *              n * nphys^2), exactly symmetric.
+ *   Other arguments as agf2_build_moments (nmom = 2 is that call).
+ * The FP64 build forms each chunk of the pair slabs once and contracts it
+ * once per moment pair (2m, 2m+1) with the columns scaled by the weight to
+ * the m-th power.
+ * Errors: as agf2_build_moments; AGF2_ERR_ARG for a bad nmom or a split
+ * precision with nmom > 2.
+ */
+agf2_status agf2_build_moments_n(agf2_handle_t handle, agf2_precision prec,
+                                 int nmom, int nphys, int naux,
+                                 const double* Lpq, int npole, int nocc_pole,
+                                 const double* e_pole, const double* u_pole,
+                                 double* m_occ, double* m_vir);
+
+/*
+ * Compression of one part of the self-energy to nmom/2 blocks of block
+ * Lanczos, conserving its moments 0 .. nmom-1 (the compression section's
+ * block Lanczos run past one block). With Lc Lc^T = m[0] (Cholesky) and
+ * M(n) = Lc^-1 m[n] Lc^-T, the Lanczos blocks are matrix polynomials in the
+ * auxiliary Hamiltonian applied to the first block, so all their products
+ * follow from the M(n): A_j = <Q_j|H|Q_j>, B_j from the Cholesky factor of
+ * the residual's overlap. The block tridiagonal matrix T (A_j on the
+ * diagonal, B_j beside it) is diagonalised, T = W diag(e) W^T, and the
+ * auxiliaries are e_aux = e and v_aux = Lc W[0:nphys], so that
+ * v_aux diag(e_aux)^n v_aux^T = m[n] for n < nmom.
+ *   m          device [nmom][nphys][nphys], symmetric, m[0] positive definite.
+ *   naux_out   host, number of auxiliaries (nmom/2 * nphys).
+ *   e_aux      device [nmom/2 * nphys] output, ascending.
+ *   v_aux      device [nphys][nmom/2 * nphys] output (row stride
+ *              nmom/2 * nphys).
+ * nmom = 2 is agf2_compress with tol = 0 (row stride nphys).
+ * Errors: AGF2_ERR_NOT_PD when m[0] or a block's residual overlap is not
+ * positive definite; AGF2_ERR_ARG for a bad nmom.
+ */
+agf2_status agf2_compress_lanczos(agf2_handle_t handle, int nphys, int nmom,
+                                  const double* m, int* naux_out,
+                                  double* e_aux, double* v_aux);
+
+/*
  * Generalised Fock matrix (Fock-matrix equation of the method review):
  *   fock = hcore + alpha * sum_rs [(pq|rs) - 1/2 (ps|rq)] rdm1[r][s]
  * rdm1 is the spin-summed density matrix. alpha = 1 is the Fock matrix;
@@ -312,10 +358,16 @@ typedef struct {
   agf2_precision prec;    /* arithmetic of the moment build                  */
   double compress_tol;    /* see agf2_compress                               */
   agf2_fock_opts fock;    /* Fock-loop options                               */
+  int nblock;             /* Lanczos blocks per part: the compression keeps
+                             moments 0 .. 2 nblock - 1 and the Green's
+                             function has nphys + 2 nblock nphys poles; above
+                             1 the moments are built in AGF2_FP64 (prec must
+                             be AGF2_FP64) and dm_init must be NULL          */
 } agf2_run_opts;
 
 /* Defaults: max_iter 20, conv_tol 1e-8, conv_tol_ipea 1e-7, diis_space 8,
- * damping 0, prec AGF2_FP64, compress_tol 0, fock as agf2_fock_opts_default. */
+ * damping 0, prec AGF2_FP64, compress_tol 0, fock as agf2_fock_opts_default,
+ * nblock 1. */
 void agf2_run_opts_default(agf2_run_opts* opts);
 
 /* One record per iteration of agf2_run. */
@@ -350,8 +402,9 @@ typedef struct {
  *              cannot be compressed, iteration 0 is redone without it
  *              (record.warm says which was used).
  *   records    host [max_iter + 1] outputs; n_records, converged host.
- *   e_pole [3 nphys], u_pole [nphys][3 nphys], rdm1 [nphys][nphys] device
- *   outputs (the final Green's function and density); nocc_pole host.
+ *   e_pole [npmax], u_pole [nphys][npmax], rdm1 [nphys][nphys] device
+ *   outputs (the final Green's function and density; npmax = nphys +
+ *   2 nblock nphys, the record's npole entries valid); nocc_pole host.
  * Returns AGF2_ERR_NO_CONVERGE when max_iter is reached (outputs valid).
  */
 agf2_status agf2_run(agf2_handle_t handle, const agf2_run_opts* opts,
@@ -366,16 +419,16 @@ agf2_status agf2_run(agf2_handle_t handle, const agf2_run_opts* opts,
  * index of the next iteration, the current Green's function poles, the
  * density, the previous moments kept for damping, the moment DIIS history
  * and the last energy, IP and EA of the convergence test) is written to a
- * host buffer of agf2_run_state_bytes(nphys, opts->diis_space) bytes (-1 for
- * bad arguments). A run continued from a saved state with the same inputs
+ * host buffer of agf2_run_state_bytes(nphys, opts) bytes (NULL opts: the
+ * defaults; -1 for bad arguments). A run continued from a saved state with the same inputs
  * and options takes exactly the iterations an uninterrupted agf2_run would
  * have taken, with bitwise equal results.
  *
  * agf2_run_resume takes the arguments of agf2_run and:
  *   state_in       host, NULL: start at iteration 0 (dm_init applies); else
  *                  continue from this saved state (dm_init is ignored).
- *                  AGF2_ERR_ARG if it was saved for another nphys or
- *                  diis_space or is not a state at all.
+ *                  AGF2_ERR_ARG if it was saved for another nphys,
+ *                  diis_space or nblock or is not a state at all.
  *   state_out      host, NULL or a buffer of agf2_run_state_bytes: the state
  *                  after the last iteration of this call (written on return
  *                  unless an error other than AGF2_ERR_NO_CONVERGE occurs).
@@ -386,7 +439,7 @@ agf2_status agf2_run(agf2_handle_t handle, const agf2_run_opts* opts,
  * the count); it must hold max_iter + 1 records. max_iter counts iterations
  * from iteration 0 of the whole run.
  */
-long agf2_run_state_bytes(int nphys, int diis_space);
+long agf2_run_state_bytes(int nphys, const agf2_run_opts* opts);
 agf2_status agf2_run_resume(agf2_handle_t handle, const agf2_run_opts* opts,
                             int nphys, int naux, const double* Lpq,
                             const double* hcore, const double* e_mf, int nocc,

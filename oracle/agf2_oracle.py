@@ -139,6 +139,49 @@ def se_moments(L, e_pole, u_pole, nocc_pole, occ_sel=None, vir_sel=None, tensors
     return m0o, m1o, m0v, m1v
 
 
+def se_moments_n(L, e_pole, u_pole, nocc_pole, nmom):
+    """Spectral moments 0..nmom-1 of the lesser and greater second-order
+    self-energy (the moment equations of the compression section, continued
+    to higher orders: the n-th moment carries the n-th power of the same
+    weight),
+        U<(n)_pq = sum_{ija} (pi|ja) [2 (qi|ja) - (qj|ia)] (e_i + e_j - e_a)^n
+        U>(n)_pq = sum_{abi} (pa|bi) [2 (qa|bi) - (qb|ai)] (e_a + e_b - e_i)^n
+    evaluated literally, one outer summed pole at a time, exactly as
+    se_moments (which is nmom = 2). Moments 0 .. 2k+1 are what a compression
+    to k + 1 Lanczos blocks conserves (the truncation family the paper names
+    AGF2(n,m), n the number of conserved self-energy moment blocks).
+    Returns (U< [nmom, N, N], U> [nmom, N, N])."""
+    N = u_pole.shape[0]
+    Q = L.shape[0]
+    eo = e_pole[:nocc_pole]
+    ev = e_pole[nocc_pole:]
+    o, v = eo.shape[0], ev.shape[0]
+    Lxo, Lxv, Lov = pole_basis_df(L, u_pole, nocc_pole)
+    Lxo_m = np.ascontiguousarray(Lxo.reshape(Q, N * o))
+    Lxv_m = np.ascontiguousarray(Lxv.reshape(Q, N * v))
+    Lov_m = np.ascontiguousarray(Lov.reshape(Q, o * v))
+    Lvo_m = np.ascontiguousarray(Lov.transpose(0, 2, 1).reshape(Q, v * o))
+    mo = np.zeros((nmom, N, N))
+    mv = np.zeros((nmom, N, N))
+    for i in range(o):
+        xija = (np.ascontiguousarray(Lxo[:, :, i].T) @ Lov_m).reshape(N, o, v)
+        xjia = (Lxo_m.T @ np.ascontiguousarray(Lov[:, i, :])).reshape(N, o, v)
+        w = (eo[i] + eo[:, None] - ev[None, :]).reshape(1, -1)
+        a = xija.reshape(N, -1)
+        t = (2.0 * xija - xjia).reshape(N, -1)
+        for n in range(nmom):
+            mo[n] += (a * w ** n) @ t.T
+    for a_ in range(v):
+        xabi = (np.ascontiguousarray(Lxv[:, :, a_].T) @ Lvo_m).reshape(N, v, o)
+        xbai = (Lxv_m.T @ np.ascontiguousarray(Lov[:, :, a_])).reshape(N, v, o)
+        w = (ev[a_] + ev[:, None] - eo[None, :]).reshape(1, -1)
+        a = xabi.reshape(N, -1)
+        t = (2.0 * xabi - xbai).reshape(N, -1)
+        for n in range(nmom):
+            mv[n] += (a * w ** n) @ t.T
+    return mo, mv
+
+
 def se_moment_elements(L, e_pole, u_pole, nocc_pole, pairs, progress=None):
     """Selected elements (p, q) of the four moments, each evaluated from the
     same literal sums as se_moments but only for the physical rows p and q
@@ -319,6 +362,83 @@ def compress(m0, m1, tol=0.0):
     M = 0.5 * (M + M.T)
     e, W = np.linalg.eigh(M)
     return e, S @ W
+
+
+def block_lanczos(moments):
+    """Compression of one part of the self-energy to nblock = len(moments)/2
+    blocks of N auxiliaries that conserve its moments 0 .. 2 nblock - 1
+    (the block-Lanczos compression of the compression section, run for
+    more than one block: the other truncations of the AGF2(n,m) family).
+
+    Reading: the self-energy part is Sigma(w) = V (w - E)^-1 V^T over its
+    (uncompressed) auxiliaries, with moments T(n) = V E^n V^T. With
+    S S^T = T(0) (lower Cholesky factor) the block Q0 = V^T S^-T is
+    orthonormal and the moments of H = diag(E) seen from it are
+    M(n) = Q0^T H^n Q0 = S^-1 T(n) S^-T (M(0) = I). Block Lanczos on H from
+    Q0,
+        H Q_j = Q_{j-1} B_j^T + Q_j A_j + Q_{j+1} B_{j+1},
+    needs only these moments: each Q_j is a polynomial in H applied to Q0,
+    Q_j = sum_m H^m Q0 C_j[m], so every inner product is
+    <Q_i|H^p|Q_j> = sum_{m,l} C_i[m]^T M(m+l+p) C_j[l]. Here
+    A_j = <Q_j|H|Q_j>; the residual R_{j+1} = H Q_j - Q_j A_j - Q_{j-1} B_j^T
+    has coefficients shifted and combined from those of Q_j and Q_{j-1};
+    B_{j+1} is the upper Cholesky factor of <R|R> (B^T B = <R|R>) and
+    Q_{j+1} = R B^-1. A_k needs moments up to 2k+1 and B_k up to 2k.
+    The block tridiagonal T (A_j on the diagonal, B_j below, B_j^T above)
+    is diagonalised, T = W diag(e) W^T; the compressed auxiliaries are
+    e and v = S W[:N], so that v diag(e)^n v^T = S (T^n)_00 S^T = T(n) for
+    n <= 2 nblock - 1. One block is compress(T(0), T(1)).
+    Raises NotPositiveDefinite when T(0) or a <R|R> is not positive
+    definite. Returns (e [nblock N], v [N, nblock N])."""
+    nm = len(moments)
+    if nm < 2 or nm % 2:
+        raise ValueError("need an even number of moments")
+    nblock = nm // 2
+    N = moments[0].shape[0]
+    try:
+        S = np.linalg.cholesky(moments[0])
+    except np.linalg.LinAlgError as exc:
+        raise NotPositiveDefinite(str(exc)) from exc
+    Sinv = np.linalg.inv(S)
+    M = [Sinv @ T @ Sinv.T for T in moments]
+    M = [0.5 * (x + x.T) for x in M]
+
+    def inner(Ci, Cj, p):
+        out = np.zeros((N, N))
+        for m, cm in enumerate(Ci):
+            for l, cl in enumerate(Cj):
+                out += cm.T @ M[m + l + p] @ cl
+        return out
+
+    C = [[np.eye(N)]]
+    A = [inner(C[0], C[0], 1)]
+    B = []
+    for j in range(1, nblock):
+        R = [np.zeros((N, N)) for _ in range(j + 1)]
+        for m, cm in enumerate(C[j - 1]):
+            R[m + 1] += cm                       # H Q_{j-1}
+            R[m] -= cm @ A[j - 1]                # - Q_{j-1} A_{j-1}
+        if j >= 2:
+            for m, cm in enumerate(C[j - 2]):
+                R[m] -= cm @ B[j - 2].T          # - Q_{j-2} B_{j-1}^T
+        G = inner(R, R, 0)
+        try:
+            Lc = np.linalg.cholesky(0.5 * (G + G.T))
+        except np.linalg.LinAlgError as exc:
+            raise NotPositiveDefinite(f"block {j}: {exc}") from exc
+        Bj = Lc.T
+        Binv = np.linalg.inv(Bj)
+        C.append([r @ Binv for r in R])
+        B.append(Bj)
+        A.append(inner(C[j], C[j], 1))
+    T = np.zeros((nblock * N, nblock * N))
+    for j in range(nblock):
+        T[j * N:(j + 1) * N, j * N:(j + 1) * N] = 0.5 * (A[j] + A[j].T)
+    for j in range(1, nblock):
+        T[j * N:(j + 1) * N, (j - 1) * N:j * N] = B[j - 1]
+        T[(j - 1) * N:j * N, j * N:(j + 1) * N] = B[j - 1].T
+    e, W = np.linalg.eigh(T)
+    return e, S @ W[:N]
 
 
 def self_energy_at(w, e_aux, v_aux):
@@ -603,14 +723,17 @@ class DIIS:
 
 
 def run_agf2(h, L, eps, nocc, max_iter=20, conv_tol=1e-8, conv_tol_ipea=1e-7,
-             diis_space=8, fock_opts=None, compress_tol=0.0, verbose=False):
+             diis_space=8, fock_opts=None, compress_tol=0.0, verbose=False, nblock=1):
     """AGF2(1,0) to self-consistency (the method as reviewed in the paper):
     start from the mean-field poles; each iteration builds the four moments
     from the current poles, extrapolates them (DIIS), compresses the lesser
     and greater parts to N auxiliaries each, relaxes the density in the Fock
     loop, and evaluates the energy and IP/EA. Converged when the energy
     changes by less than conv_tol and IP/EA by less than conv_tol_ipea.
-    Stops unconverged when a Fock loop reaches its cycle limit."""
+    Stops unconverged when a Fock loop reaches its cycle limit.
+    nblock > 1: each part is compressed to nblock Lanczos blocks conserving
+    moments 0 .. 2 nblock - 1 (block_lanczos), so the Green's function has
+    N + 2 nblock N poles."""
     fock_opts = dict(fock_opts or {})
     N = eps.shape[0]
     nelec = 2 * nocc
@@ -622,14 +745,23 @@ def run_agf2(h, L, eps, nocc, max_iter=20, conv_tol=1e-8, conv_tol_ipea=1e-7,
     hist = []
     prev = None
     converged = False
+    nmom = 2 * nblock
     for it in range(max_iter + 1):
-        m = se_moments(L, e_pole, u_pole, nocc_pole)
+        if nblock == 1:
+            m = se_moments(L, e_pole, u_pole, nocc_pole)
+        else:
+            mo, mv = se_moments_n(L, e_pole, u_pole, nocc_pole, nmom)
+            m = tuple(mo) + tuple(mv)
         if diis is not None:
             flat = diis.update(np.concatenate([x.ravel() for x in m]))
-            m = tuple(flat[k * N * N:(k + 1) * N * N].reshape(N, N) for k in range(4))
+            m = tuple(flat[k * N * N:(k + 1) * N * N].reshape(N, N) for k in range(2 * nmom))
         m = tuple(0.5 * (x + x.T) for x in m)
-        eo, vo = compress(m[0], m[1], tol=compress_tol)
-        ev, vv = compress(m[2], m[3], tol=compress_tol)
+        if nblock == 1:
+            eo, vo = compress(m[0], m[1], tol=compress_tol)
+            ev, vv = compress(m[2], m[3], tol=compress_tol)
+        else:
+            eo, vo = block_lanczos(m[:nmom])
+            ev, vv = block_lanczos(m[nmom:])
         e_aux = np.concatenate([eo, ev])
         v_aux = np.hstack([vo, vv])
         fl = fock_loop(h, L, nelec, e_aux, v_aux, D, **fock_opts)

@@ -40,7 +40,8 @@ class FockOpts(ctypes.Structure):
 
 class RunOpts(ctypes.Structure):
     _fields_ = [("max_iter", _I), ("conv_tol", _D), ("conv_tol_ipea", _D), ("diis_space", _I),
-                ("damping", _D), ("prec", _I), ("compress_tol", _D), ("fock", FockOpts)]
+                ("damping", _D), ("prec", _I), ("compress_tol", _D), ("fock", FockOpts),
+                ("nblock", _I)]
 
 
 class IterRecord(ctypes.Structure):
@@ -63,6 +64,8 @@ SIGNATURES = {
     "agf2_synchronize": (_I, [_P]),
     "agf2_build_moments": (_I, [_P, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P, _P]),
     "agf2_build_moments_batched": (_I, [_P, _I, ctypes.POINTER(System), _IP]),
+    "agf2_build_moments_n": (_I, [_P, _I, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P]),
+    "agf2_compress_lanczos": (_I, [_P, _I, _I, _P, _IP, _P, _P]),
     "agf2_fock_build": (_I, [_P, _I, _I, _P, _P, _P, _D, _P]),
     "agf2_compress": (_I, [_P, _I, _P, _P, _D, _IP, _P, _P]),
     "agf2_fock_opts_default": (None, [ctypes.POINTER(FockOpts)]),
@@ -75,7 +78,7 @@ SIGNATURES = {
     "agf2_run_opts_default": (None, [ctypes.POINTER(RunOpts)]),
     "agf2_run": (_I, [_P, ctypes.POINTER(RunOpts), _I, _I, _P, _P, _P, _I, _P,
                       ctypes.POINTER(IterRecord), _IP, _IP, _P, _P, _IP, _P]),
-    "agf2_run_state_bytes": (ctypes.c_long, [_I, _I]),
+    "agf2_run_state_bytes": (ctypes.c_long, [_I, ctypes.POINTER(RunOpts)]),
     "agf2_run_resume": (_I, [_P, ctypes.POINTER(RunOpts), _I, _I, _P, _P, _P, _I, _P, _P, _P,
                              _I, ctypes.POINTER(IterRecord), _IP, _IP, _P, _P, _IP, _P]),
     "agf2_mlp_create": (_I, [_P, ctypes.POINTER(_P)]),
@@ -205,6 +208,35 @@ def agf2_build_moments(h: Handle, L, e_pole, u_pole, nocc_pole: int, prec="fp64"
         h.h, p, nphys, naux, _ptr(L, "L", d), npole, nocc_pole, _ptr(e_pole, "e_pole", d),
         _ptr(u_pole, "u_pole", d), *[_ptr(m, "moment", d) for m in out]))
     return out
+
+
+def agf2_build_moments_n(h: Handle, L, e_pole, u_pole, nocc_pole: int, nmom: int, prec="fp64"):
+    """Moments 0..nmom-1 of each part: (m_occ [nmom, N, N], m_vir [nmom, N, N])."""
+    naux, nphys, _ = L.shape
+    npole = e_pole.shape[0]
+    mo = h.empty(nmom, nphys, nphys)
+    mv = h.empty(nmom, nphys, nphys)
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    d = h.device
+    h._check(h.lib.agf2_build_moments_n(
+        h.h, p, int(nmom), nphys, naux, _ptr(L, "L", d), npole, nocc_pole,
+        _ptr(e_pole, "e_pole", d), _ptr(u_pole, "u_pole", d), _ptr(mo, "m_occ", d),
+        _ptr(mv, "m_vir", d)))
+    return mo, mv
+
+
+def agf2_compress_lanczos(h: Handle, m):
+    """Compression of one part to nmom/2 Lanczos blocks from its moments m
+    [nmom, N, N]: (naux, e_aux [naux], v_aux [N, naux])."""
+    nmom, nphys, _ = m.shape
+    nb = nmom // 2
+    e = h.empty(nb * nphys)
+    v = h.empty(nphys, nb * nphys if nb > 1 else nphys)
+    n = ctypes.c_int(0)
+    d = h.device
+    h._check(h.lib.agf2_compress_lanczos(h.h, nphys, int(nmom), _ptr(m, "m", d), ctypes.byref(n),
+                                         _ptr(e, "e_aux", d), _ptr(v, "v_aux", d)))
+    return n.value, e[:n.value], v[:, :n.value]
 
 
 def agf2_build_moments_batched(h: Handle, systems, outs=None):
@@ -369,8 +401,9 @@ def agf2_run(h: Handle, L, hcore, e_mf, nocc: int, opts: RunOpts = None, dm_init
     nrec = ctypes.c_int(0)
     conv = ctypes.c_int(0)
     nocc_pole = ctypes.c_int(0)
-    e_pole = h.empty(3 * nphys)
-    u_pole = h.empty(nphys, 3 * nphys)
+    npmax = nphys * (1 + 2 * max(1, opts.nblock))
+    e_pole = h.empty(npmax)
+    u_pole = h.empty(nphys, npmax)
     rdm1 = h.empty(nphys, nphys)
     d = h.device
     st = h.lib.agf2_run(h.h, ctypes.byref(opts), nphys, naux, _ptr(L, "L", d),
@@ -398,9 +431,9 @@ def agf2_run_resume(h: Handle, L, hcore, e_mf, nocc: int, opts: RunOpts = None, 
     import numpy as np
     naux, nphys, _ = L.shape
     opts = run_opts() if opts is None else opts
-    nbytes = h.lib.agf2_run_state_bytes(nphys, opts.diis_space)
+    nbytes = h.lib.agf2_run_state_bytes(nphys, ctypes.byref(opts))
     if nbytes < 0:
-        raise ValueError("bad nphys or diis_space")
+        raise ValueError("bad nphys or run options")
     sin = None
     if state_in is not None:
         sin = np.ascontiguousarray(state_in, dtype=np.uint8)
@@ -411,8 +444,9 @@ def agf2_run_resume(h: Handle, L, hcore, e_mf, nocc: int, opts: RunOpts = None, 
     nrec = ctypes.c_int(0)
     conv = ctypes.c_int(0)
     nocc_pole = ctypes.c_int(0)
-    e_pole = h.empty(3 * nphys)
-    u_pole = h.empty(nphys, 3 * nphys)
+    npmax = nphys * (1 + 2 * max(1, opts.nblock))
+    e_pole = h.empty(npmax)
+    u_pole = h.empty(nphys, npmax)
     rdm1 = h.empty(nphys, nphys)
     d = h.device
     st = h.lib.agf2_run_resume(

@@ -360,6 +360,163 @@ int compress_impl(Handle& h, int N, const double* m0, const double* m1, double t
   return k;
 }
 
+// ------------------------------------------------------- Lanczos blocks
+
+// I (N x N)
+__global__ void set_identity(int N, double* A) {
+  const long nn = (long)N * N;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nn;
+       i += (long)gridDim.x * blockDim.x)
+    A[i] = (i / N == i % N) ? 1.0 : 0.0;
+}
+
+// column-major n x n T: block at (r0, c0) = src (N x N, column-major) or its
+// transpose
+__global__ void put_block(int n, double* T, int r0, int c0, int N, const double* src,
+                          int trans) {
+  const long nn = (long)N * N;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nn;
+       i += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(i % N), c = (int)(i / N);
+    T[(long)(r0 + r) + (long)(c0 + c) * n] = trans ? src[(long)c + (long)r * N] : src[i];
+  }
+}
+
+}  // namespace
+
+// Compression of one part to nb blocks of block Lanczos from its moments
+// m[0 .. 2nb-1] (compression section, more than one block). Column-major
+// throughout (the symmetric inputs read the same either way):
+//   Lc Lc^T = T(0); M(n) = Lc^-1 T(n) Lc^-T, M(0) = I;
+//   Lanczos vectors as matrix polynomials Q_j = sum_m H^m Q_0 C_j[m], so
+//   <Q_i|H^p|Q_j> = sum_{m,l} C_i[m]^T M(m+l+p) C_j[l];
+//   A_j = <Q_j|H|Q_j>; R = H Q_{j-1} - Q_{j-1} A_{j-1} - Q_{j-2} B_{j-1}^T;
+//   Lg Lg^T = <R|R>, B_j = Lg^T, C_j = R Lg^-T;
+//   T = blocks A_j on the diagonal, B_j below, B_j^T above; T = W e W^T;
+//   v_aux = Lc W[0:N] (row-major [N][nb N]), e_aux = e.
+int compress_lanczos_impl(Handle& h, int N, int nb, const double* m, double* e_aux,
+                          double* v_aux) {
+  const long nn = (long)N * N;
+  if (nb == 1) return compress_impl(h, N, m, m + nn, 0.0, e_aux, v_aux);
+  hipStream_t st = h.stream;
+  const int nm = 2 * nb, n = nb * N;
+  const long ncoef = (long)nb * (nb + 1) / 2;
+  ProfScope ps(h, "compress", (4.0 * nb * nb * nb + 2.0 * nm) * (double)nn * N +
+                                  9.0 * (double)n * n * n,
+               8.0 * (nm + 2.0 * nb) * nn);
+  double* Lc = h.ws_misc[0].as<double>(nn);
+  double* M = h.ws_misc[1].as<double>(nm * nn);
+  double* C = h.ws_misc[3].as<double>(ncoef * nn);   // C_j[m] at (j(j+1)/2 + m) nn
+  double* R = h.ws_misc[4].as<double>((long)nb * nn);
+  double* A = h.ws_misc[5].as<double>(2L * nb * nn);   // A_j, then Lg_j
+  double* Lg = A + (long)nb * nn;
+  double* tmp = h.ws_misc[6].as<double>(2 * nn);
+  double* T = h.ws_misc[7].as<double>((long)n * n + 2L * n + 8);
+  double* E = T + (long)n * n;
+  int* info = reinterpret_cast<int*>(E + 2L * n);
+  auto coef = [&](int j, int k) { return C + ((long)j * (j + 1) / 2 + k) * nn; };
+  auto mm = [&](double* Cm, const double* Am, bool ta, const double* Bm, bool tb, double alpha,
+                double beta) {
+    Gemm g;
+    g.M = N; g.N = N; g.K = N;
+    g.A = Am; g.sAm = ta ? N : 1; g.sAk = ta ? 1 : N;
+    g.B = Bm; g.sBk = tb ? N : 1; g.sBn = tb ? 1 : N;
+    g.C = Cm; g.sCm = 1; g.sCn = N;
+    g.alpha = alpha; g.beta = beta;
+    gemm_f64(g, st);
+  };
+  const double one = 1.0;
+  // Cholesky factor of T(0)
+  AGF2_HIP(hipMemcpyAsync(Lc, m, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  AGF2_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_lower, N, Lc, N, info));
+  if (const int inf = read_info(h, info))
+    throw Error{AGF2_ERR_NOT_PD, "zeroth moment is not positive definite (Cholesky pivot " +
+                                     std::to_string(inf) + ")"};
+  hipLaunchKernelGGL(zero_colmajor_upper, dim3(nblk(nn)), dim3(256), 0, st, N, Lc);
+  AGF2_CHECK_LAUNCH();
+  // orthonormalised moments
+  hipLaunchKernelGGL(set_identity, dim3(nblk(nn)), dim3(256), 0, st, N, M);
+  AGF2_CHECK_LAUNCH();
+  for (int k = 1; k < nm; ++k) {
+    double* Mk = M + k * nn;
+    AGF2_HIP(hipMemcpyAsync(Mk, m + k * nn, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+    AGF2_BLAS(rocblas_dtrsm(h.blas, rocblas_side_left, rocblas_fill_lower,
+                            rocblas_operation_none, rocblas_diagonal_non_unit, N, N, &one, Lc, N,
+                            Mk, N));
+    AGF2_BLAS(rocblas_dtrsm(h.blas, rocblas_side_right, rocblas_fill_lower,
+                            rocblas_operation_transpose, rocblas_diagonal_non_unit, N, N, &one,
+                            Lc, N, Mk, N));
+    symmetrize_f64(N, Mk, st);
+  }
+  // out = sum_{a<ni, b<nj} Ci[a]^T M(a+b+p) Cj[b]
+  auto inner = [&](const double* Ci, int ni, const double* Cj, int nj, int p, double* out) {
+    for (int a = 0; a < ni; ++a) {
+      for (int b = 0; b < nj; ++b)
+        mm(tmp, M + (a + b + p) * nn, false, Cj + b * nn, false, 1.0, b == 0 ? 0.0 : 1.0);
+      mm(out, Ci + a * nn, true, tmp, false, 1.0, a == 0 ? 0.0 : 1.0);
+    }
+    symmetrize_f64(N, out, st);
+  };
+  hipLaunchKernelGGL(set_identity, dim3(nblk(nn)), dim3(256), 0, st, N, coef(0, 0));
+  AGF2_CHECK_LAUNCH();
+  inner(coef(0, 0), 1, coef(0, 0), 1, 1, A);
+  for (int j = 1; j < nb; ++j) {
+    // coefficients of R = H Q_{j-1} - Q_{j-1} A_{j-1} - Q_{j-2} B_{j-1}^T
+    fill_zero(R, (long)(j + 1) * nn, st);
+    for (int k = 0; k < j; ++k) {
+      axpby_f64(nn, 1.0, coef(j - 1, k), 1.0, R + (k + 1) * nn, st);
+      mm(R + k * nn, coef(j - 1, k), false, A + (long)(j - 1) * nn, false, -1.0, 1.0);
+    }
+    if (j >= 2)   // B_{j-1}^T = Lg_{j-1}
+      for (int k = 0; k < j - 1; ++k)
+        mm(R + k * nn, coef(j - 2, k), false, Lg + (long)(j - 1) * nn, false, -1.0, 1.0);
+    double* L_j = Lg + (long)j * nn;
+    inner(R, j + 1, R, j + 1, 0, L_j);
+    AGF2_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_lower, N, L_j, N, info));
+    if (const int inf = read_info(h, info))
+      throw Error{AGF2_ERR_NOT_PD, "Lanczos block " + std::to_string(j) +
+                                       " is not positive definite (Cholesky pivot " +
+                                       std::to_string(inf) + ")"};
+    hipLaunchKernelGGL(zero_colmajor_upper, dim3(nblk(nn)), dim3(256), 0, st, N, L_j);
+    AGF2_CHECK_LAUNCH();
+    for (int k = 0; k <= j; ++k) {
+      AGF2_BLAS(rocblas_dtrsm(h.blas, rocblas_side_right, rocblas_fill_lower,
+                              rocblas_operation_transpose, rocblas_diagonal_non_unit, N, N, &one,
+                              L_j, N, R + k * nn, N));
+      AGF2_HIP(hipMemcpyAsync(coef(j, k), R + k * nn, nn * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+    }
+    inner(coef(j, 0), j + 1, coef(j, 0), j + 1, 1, A + (long)j * nn);
+  }
+  // block tridiagonal matrix and its eigendecomposition
+  fill_zero(T, (long)n * n, st);
+  for (int j = 0; j < nb; ++j) {
+    hipLaunchKernelGGL(put_block, dim3(nblk(nn)), dim3(256), 0, st, n, T, j * N, j * N, N,
+                       A + (long)j * nn, 0);
+    if (j > 0) {
+      // below: B_j = Lg_j^T; above: B_j^T = Lg_j
+      hipLaunchKernelGGL(put_block, dim3(nblk(nn)), dim3(256), 0, st, n, T, j * N, (j - 1) * N,
+                         N, Lg + (long)j * nn, 1);
+      hipLaunchKernelGGL(put_block, dim3(nblk(nn)), dim3(256), 0, st, n, T, (j - 1) * N, j * N,
+                         N, Lg + (long)j * nn, 0);
+    }
+    AGF2_CHECK_LAUNCH();
+  }
+  AGF2_BLAS(rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_lower, n, T, n, e_aux,
+                             E, info));
+  if (read_info(h, info) != 0) throw Error{AGF2_ERR_HIP, "syevd failed in compression"};
+  // v_aux[p][k] = sum_j Lc(p, j) W(j, k)
+  Gemm g;
+  g.M = N; g.N = n; g.K = N;
+  g.A = Lc; g.sAm = 1; g.sAk = N;
+  g.B = T; g.sBk = 1; g.sBn = n;
+  g.C = v_aux; g.sCm = n; g.sCn = 1;
+  gemm_f64(g, st);
+  return n;
+}
+
+namespace {
+
 // ------------------------------------------------------------ Fock loop
 
 struct Aufbau {
@@ -959,6 +1116,56 @@ agf2_status agf2_build_moments(agf2_handle_t hh, agf2_precision prec, int nphys,
         .run();
     build_moments(h, prec, nphys, naux, Lpq, npole, nocc_pole, e_pole, u_pole, m0_occ, m1_occ,
                   m0_vir, m1_vir);
+  });
+}
+
+agf2_status agf2_build_moments_n(agf2_handle_t hh, agf2_precision prec, int nmom, int nphys,
+                                 int naux, const double* Lpq, int npole, int nocc_pole,
+                                 const double* e_pole, const double* u_pole, double* m_occ,
+                                 double* m_vir) {
+  return guarded(hh, [&](Handle& h) {
+    AGF2_REQUIRE(nmom >= 2 && nmom % 2 == 0 && nmom <= 16, "nmom must be even, 2..16");
+    AGF2_REQUIRE(nphys >= 1 && naux >= 1, "nphys and naux must be >= 1");
+    AGF2_REQUIRE(npole >= 2 && nocc_pole >= 1 && nocc_pole < npole,
+                 "need 1 <= nocc_pole < npole");
+    AGF2_REQUIRE(Lpq && e_pole && u_pole && m_occ && m_vir, "NULL array argument");
+    AGF2_REQUIRE(prec == AGF2_FP64 || nmom == 2,
+                 "moments beyond the first are built in AGF2_FP64 only");
+    FiniteCheck(h)
+        .add(Lpq, (long)naux * nphys * nphys, "Lpq")
+        .add(e_pole, npole, "e_pole")
+        .add(u_pole, (long)nphys * npole, "u_pole")
+        .run();
+    const long nn = (long)nphys * nphys;
+    if (prec != AGF2_FP64) {
+      build_moments(h, prec, nphys, naux, Lpq, npole, nocc_pole, e_pole, u_pole, m_occ,
+                    m_occ + nn, m_vir, m_vir + nn);
+      return;
+    }
+    std::vector<double*> uo(nmom), uv(nmom);
+    for (int k = 0; k < nmom; ++k) {
+      uo[k] = m_occ + k * nn;
+      uv[k] = m_vir + k * nn;
+    }
+    build_moments_f64_n(h, nphys, naux, Lpq, npole, nocc_pole, e_pole, u_pole, nmom / 2,
+                        uo.data(), uv.data());
+  });
+}
+
+agf2_status agf2_compress_lanczos(agf2_handle_t hh, int nphys, int nmom, const double* m,
+                                  int* naux_out, double* e_aux, double* v_aux) {
+  return guarded(hh, [&](Handle& h) {
+    AGF2_REQUIRE(nphys >= 1, "nphys must be >= 1");
+    AGF2_REQUIRE(nmom >= 2 && nmom % 2 == 0 && nmom <= 16, "nmom must be even, 2..16");
+    AGF2_REQUIRE(m && naux_out && e_aux && v_aux, "NULL argument");
+    *naux_out = 0;
+    FiniteCheck(h).add(m, (long)nmom * nphys * nphys, "m").run();
+    if (nmom == 2) {
+      // one block: the compression itself, with v_aux's row stride nphys
+      *naux_out = compress_impl(h, nphys, m, m + (long)nphys * nphys, 0.0, e_aux, v_aux);
+      return;
+    }
+    *naux_out = compress_lanczos_impl(h, nphys, nmom / 2, m, e_aux, v_aux);
   });
 }
 

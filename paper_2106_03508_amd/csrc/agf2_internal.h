@@ -132,6 +132,14 @@ void lov_transform_blas(Handle& h, int N, int Q, int Qp, const double* u, int np
 void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
                        int nocc, const double* e, const double* u, double* m0o,
                        double* m1o, double* m0v, double* m1v);
+// Moments 0 .. 2 npm - 1 of each part (Uo[k], Uv[k] are [N][N] outputs).
+void build_moments_f64_n(Handle& h, int N, int Q, const double* L, int npole, int nocc,
+                         const double* e, const double* u, int npm, double* const* Uo,
+                         double* const* Uv);
+// Compression of one part to nblock Lanczos blocks from its moments
+// m[0 .. 2 nblock - 1] ([N][N] each, contiguous); returns nblock * N.
+int compress_lanczos_impl(Handle& h, int N, int nblock, const double* m, double* e_aux,
+                          double* v_aux);
 void build_moments_split(Handle& h, int N, int Q, const double* L, int npole,
                          int nocc, const double* e, const double* u,
                          double* m0o, double* m1o, double* m0v, double* m1v,

@@ -170,8 +170,8 @@ namespace {
 // Saved state of agf2_run between iterations (host blob, see
 // agf2_run_state_bytes): a fixed header, then the device arrays in order.
 struct RunStateHeader {
-  char magic[8];          // "AGF2RUN1"
-  int nphys, diis_space;
+  char magic[8];          // "AGF2RUN2"
+  int nphys, diis_space, nblock;
   int next_iter;          // index of the next iteration to run
   int npole, nocc_pole;
   int have_prev;          // a previous iteration's E, IP, EA exist
@@ -180,10 +180,12 @@ struct RunStateHeader {
   double prev_e, prev_ip, prev_ea;
 };
 
-long state_doubles(int N, int space) {
+// poles, amplitudes, density, previous moments, moment DIIS history
+long state_doubles(int N, int space, int nb) {
   const long nn = (long)N * N;
-  return 3L * N + 3L * N * N + nn + 4 * nn + 4 * nn + (long)std::max(space, 1) * 2 * 4 * nn +
-         (long)std::max(space, 1) * std::max(space, 1);
+  const long npmax = (long)N * (1 + 2 * nb), len = 4L * nb * nn;
+  const long sp = std::max(space, 1);
+  return npmax + (long)N * npmax + nn + len + len + sp * 2 * len + sp * sp;
 }
 
 }  // namespace
@@ -210,12 +212,16 @@ agf2_status run_impl(Handle& h, const agf2_run_opts* opts, int nphys, int naux, 
                      nocc_pole && rdm1,
                  "NULL argument");
     AGF2_REQUIRE(o.max_iter >= 0 && o.diis_space >= 0 && o.diis_space <= 64 &&
-                     o.damping >= 0.0 && o.damping < 1.0,
+                     o.damping >= 0.0 && o.damping < 1.0 && o.nblock >= 1 && o.nblock <= 8,
                  "bad run options");
+    AGF2_REQUIRE(o.nblock == 1 || (o.prec == AGF2_FP64 && dm_init == nullptr),
+                 "nblock > 1 needs prec AGF2_FP64 and no dm_init");
     hipStream_t st = h.stream;
     const int N = nphys;
     const long nn = (long)N * N;
-    const int nmax = 3 * N;
+    const int nb = o.nblock, nmom = 2 * nb;
+    const int nmax = N * (1 + 2 * nb);   // poles: N + 2 nb N
+    const long nbn = (long)nb * N;       // auxiliaries per part
     FiniteCheck(h)
         .add(Lpq, (long)naux * nn, "Lpq")
         .add(hcore, nn, "hcore")
@@ -229,29 +235,29 @@ agf2_status run_impl(Handle& h, const agf2_run_opts* opts, int nphys, int naux, 
     double* u_cur = e_new + nmax;
     double* u_new = u_cur + (long)N * nmax;
     double* small = u_new + (long)N * nmax;   // 2 column weights
-    double* m = h.ws_run[1].as<double>(8 * nn);
-    double* mprev = m + 4 * nn;
-    double* a = h.ws_run[2].as<double>(2L * N + 2 * nn + 2L * N + 2 * nn + nn);
+    double* m = h.ws_run[1].as<double>(4L * nmom * nn);
+    double* mprev = m + 2L * nmom * nn;
+    double* a = h.ws_run[2].as<double>(4 * nbn + 4 * N * nbn + nn);
     double* eo = a;
-    double* vo = eo + N;
-    double* ev = vo + nn;
-    double* vv = ev + N;
-    double* e_se = vv + nn;
-    double* v_se = e_se + 2L * N;
-    double* fock = v_se + 2 * nn;
-    double* vo_p = h.ws_run[3].as<double>(2 * nn);
-    double* vv_p = vo_p + nn;
+    double* vo = eo + nbn;
+    double* ev = vo + N * nbn;
+    double* vv = ev + nbn;
+    double* e_se = vv + N * nbn;
+    double* v_se = e_se + 2 * nbn;
+    double* fock = v_se + 2 * N * nbn;
+    double* vo_p = h.ws_run[3].as<double>(2 * N * nbn);
+    double* vv_p = vo_p + N * nbn;
     int npole = N, nocc_p = nocc;
-    MomentDiis diis(h, 4 * nn, o.diis_space);
+    MomentDiis diis(h, 2L * nmom * nn, o.diis_space);
     bool conv = false, have_prev = false, fock_failed = false;
     double prev_e = 0, prev_ip = 0, prev_ea = 0;
     int it0 = 0;
     if (state_in) {
       RunStateHeader hd;
       std::memcpy(&hd, state_in, sizeof hd);
-      AGF2_REQUIRE(std::memcmp(hd.magic, "AGF2RUN1", 8) == 0, "state_in is not an agf2_run state");
-      AGF2_REQUIRE(hd.nphys == N && hd.diis_space == o.diis_space,
-                   "state_in was saved for another nphys or diis_space");
+      AGF2_REQUIRE(std::memcmp(hd.magic, "AGF2RUN2", 8) == 0, "state_in is not an agf2_run state");
+      AGF2_REQUIRE(hd.nphys == N && hd.diis_space == o.diis_space && hd.nblock == nb,
+                   "state_in was saved for another nphys, diis_space or nblock");
       AGF2_REQUIRE(hd.npole >= 2 && hd.npole <= nmax && hd.nocc_pole >= 1 &&
                        hd.nocc_pole < hd.npole && hd.next_iter >= 1 &&
                        hd.diis_n >= 0 && hd.diis_n <= o.diis_space,
@@ -272,7 +278,7 @@ agf2_status run_impl(Handle& h, const agf2_run_opts* opts, int nphys, int naux, 
       up(e_cur, nmax);
       up(u_cur, (long)N * nmax);
       up(rdm1, nn);
-      up(mprev, 4 * nn);
+      up(mprev, 2L * nmom * nn);
       diis.restore(hd.diis_have_prev != 0, hd.diis_order, hd.diis_n, d);
       AGF2_HIP(hipStreamSynchronize(st));
     } else {
@@ -291,19 +297,34 @@ agf2_status run_impl(Handle& h, const agf2_run_opts* opts, int nphys, int naux, 
       bool warm = (it == 0 && dm_init != nullptr);
       int no = 0, nv = 0;
       for (int attempt = 0; attempt < 2; ++attempt) {
-        build_moments(h, o.prec, N, naux, Lpq, npole, nocc_p, e_cur, u_cur, m, m + nn,
-                      m + 2 * nn, m + 3 * nn);
+        if (nb == 1) {
+          build_moments(h, o.prec, N, naux, Lpq, npole, nocc_p, e_cur, u_cur, m, m + nn,
+                        m + 2 * nn, m + 3 * nn);
+        } else {
+          std::vector<double*> uo(nmom), uv(nmom);
+          for (int k = 0; k < nmom; ++k) {
+            uo[k] = m + k * nn;
+            uv[k] = m + (nmom + k) * nn;
+          }
+          build_moments_f64_n(h, N, naux, Lpq, npole, nocc_p, e_cur, u_cur, nb, uo.data(),
+                              uv.data());
+        }
         if (warm) axpby_f64(4 * nn, 1.0, dm_init, 1.0, m, st);
         if (o.damping > 0.0 && it > 0)
-          axpby_f64(4 * nn, o.damping, mprev, 1.0 - o.damping, m, st);
+          axpby_f64(2L * nmom * nn, o.damping, mprev, 1.0 - o.damping, m, st);
         if (!warm) diis.update(m);
-        for (int k = 0; k < 4; ++k) symmetrize_f64(N, m + k * nn, st);
+        for (int k = 0; k < 2 * nmom; ++k) symmetrize_f64(N, m + k * nn, st);
         AGF2_HIP(hipStreamSynchronize(st));
         rec.t_moments = now() - t0;
         t0 = now();
         try {
-          no = compress_part(h, N, m, m + nn, o.compress_tol, eo, vo);
-          nv = compress_part(h, N, m + 2 * nn, m + 3 * nn, o.compress_tol, ev, vv);
+          if (nb == 1) {
+            no = compress_part(h, N, m, m + nn, o.compress_tol, eo, vo);
+            nv = compress_part(h, N, m + 2 * nn, m + 3 * nn, o.compress_tol, ev, vv);
+          } else {
+            no = compress_lanczos_impl(h, N, nb, m, eo, vo);
+            nv = compress_lanczos_impl(h, N, nb, m + nmom * nn, ev, vv);
+          }
         } catch (const Error& e) {
           if (warm && e.status == AGF2_ERR_NOT_PD) {   // fall back to the cold start
             warm = false;
@@ -319,19 +340,22 @@ agf2_status run_impl(Handle& h, const agf2_run_opts* opts, int nphys, int naux, 
         diis.update(m);
       }
       rec.warm = warm ? 1 : 0;
-      AGF2_HIP(hipMemcpyAsync(mprev, m, 4 * nn * sizeof(double), hipMemcpyDeviceToDevice, st));
-      // pack the auxiliaries: e_se = [eo, ev], v_se = [vo | vv]
+      AGF2_HIP(hipMemcpyAsync(mprev, m, 2L * nmom * nn * sizeof(double), hipMemcpyDeviceToDevice,
+                              st));
+      // pack the auxiliaries: e_se = [eo, ev], v_se = [vo | vv]; one block's
+      // couplings have row stride N, several blocks' row stride nb N
       const int ns = no + nv;
+      const long ldv = nb == 1 ? (long)N : nbn;
       AGF2_HIP(hipMemcpyAsync(e_se, eo, no * sizeof(double), hipMemcpyDeviceToDevice, st));
       AGF2_HIP(hipMemcpyAsync(e_se + no, ev, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
       hipLaunchKernelGGL(copy_cols, dim3(nblk((long)N * no)), dim3(256), 0, st, N, no, vo,
-                         (long)N, v_se, (long)ns, 0);
+                         ldv, v_se, (long)ns, 0);
       hipLaunchKernelGGL(copy_cols, dim3(nblk((long)N * nv)), dim3(256), 0, st, N, nv, vv,
-                         (long)N, v_se, (long)ns, no);
+                         ldv, v_se, (long)ns, no);
       hipLaunchKernelGGL(copy_cols, dim3(nblk((long)N * no)), dim3(256), 0, st, N, no, vo,
-                         (long)N, vo_p, (long)no, 0);
+                         ldv, vo_p, (long)no, 0);
       hipLaunchKernelGGL(copy_cols, dim3(nblk((long)N * nv)), dim3(256), 0, st, N, nv, vv,
-                         (long)N, vv_p, (long)nv, 0);
+                         ldv, vv_p, (long)nv, 0);
       AGF2_CHECK_LAUNCH();
       AGF2_HIP(hipStreamSynchronize(st));
       rec.t_compress = now() - t0;
@@ -400,9 +424,10 @@ agf2_status run_impl(Handle& h, const agf2_run_opts* opts, int nphys, int naux, 
     if (state_out) {
       RunStateHeader hd;
       std::memset(&hd, 0, sizeof hd);
-      std::memcpy(hd.magic, "AGF2RUN1", 8);
+      std::memcpy(hd.magic, "AGF2RUN2", 8);
       hd.nphys = N;
       hd.diis_space = o.diis_space;
+      hd.nblock = nb;
       hd.next_iter = it;
       hd.npole = npole;
       hd.nocc_pole = nocc_p;
@@ -422,7 +447,7 @@ agf2_status run_impl(Handle& h, const agf2_run_opts* opts, int nphys, int naux, 
       down(e_cur, nmax);
       down(u_cur, (long)N * nmax);
       down(rdm1, nn);
-      down(mprev, 4 * nn);
+      down(mprev, 2L * nmom * nn);
       diis.save(d, st);
     }
     AGF2_HIP(hipStreamSynchronize(st));
@@ -467,11 +492,16 @@ void agf2_run_opts_default(agf2_run_opts* o) {
   o->prec = AGF2_FP64;
   o->compress_tol = 0.0;
   agf2_fock_opts_default(&o->fock);
+  o->nblock = 1;
 }
 
-long agf2_run_state_bytes(int nphys, int diis_space) {
-  if (nphys < 1 || diis_space < 0 || diis_space > 64) return -1;
-  return (long)sizeof(RunStateHeader) + 8L * state_doubles(nphys, diis_space);
+long agf2_run_state_bytes(int nphys, const agf2_run_opts* opts) {
+  agf2_run_opts o;
+  agf2_run_opts_default(&o);
+  if (opts) o = *opts;
+  if (nphys < 1 || o.diis_space < 0 || o.diis_space > 64 || o.nblock < 1 || o.nblock > 8)
+    return -1;
+  return (long)sizeof(RunStateHeader) + 8L * state_doubles(nphys, o.diis_space, o.nblock);
 }
 
 agf2_status agf2_run(agf2_handle_t hh, const agf2_run_opts* opts, int nphys, int naux,

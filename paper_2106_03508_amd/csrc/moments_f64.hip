@@ -481,16 +481,32 @@ long ndiag(const PairTable& t, int P0, int P1) {
 
 }  // namespace
 
-// One part (lesser or greater) of the moment build.
+namespace {
+
+// Z[x][c] *= w[c] for the chunk's Kc columns (row stride ldz)
+__global__ void scale_cols_kernel(int N, long Kc, long ldz, const double* w, double* Z) {
+  const long tot = (long)N * Kc;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < tot;
+       i += (long)gridDim.x * blockDim.x) {
+    const long x = i / Kc, c = i % Kc;
+    Z[x * ldz + c] *= w[c];
+  }
+}
+
+}  // namespace
+
+// One part (lesser or greater) of the moment build: moments 0 .. 2 npm - 1
+// into U[0 .. 2 npm - 1]. Each Z chunk feeds one SYRK per moment pair: pair m
+// (moments 2m and 2m + 1) is the SYRK of Z diag(w)^m, whose columns are
+// scaled by w in place before each further pair.
 static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, long sRp,
                              long sRx, const double* S, long sSp, long sSc,
-                             const double* ep, int np, const double* ec, int nc,
-                             double* U0, double* U1) {
+                             const double* ep, int np, const double* ec, int nc, int npm,
+                             double* const* U) {
   hipStream_t st = h.stream;
   const long nn = (long)N * N;
   if (np == 0 || nc == 0) {
-    fill_zero(U0, nn, st);
-    fill_zero(U1, nn, st);
+    for (int k = 0; k < 2 * npm; ++k) fill_zero(U[k], nn, st);
     return;
   }
   PairTable t = make_pairs(np, nc);
@@ -516,8 +532,9 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
   const int nlower = tiles_n * (tiles_n + 1) / 2;
   const int nsplit_max = std::max(1, std::min(64, (2048 + nlower - 1) / nlower));
   const long part_stride = 2 * nn;
-  double* part = h.ws_moments[5].as<double>(part_stride * nsplit_max);
-  fill_zero(part, part_stride * nsplit_max, st);
+  const long pair_stride = part_stride * nsplit_max;
+  double* part = h.ws_moments[5].as<double>(pair_stride * npm);
+  fill_zero(part, pair_stride * npm, st);
 
   const int tc = slab_f64_tc(nc);
   int P0 = 0;
@@ -550,15 +567,23 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
     SyrkF64 ya;
     ya.Z = Z; ya.ldz = kcap; ya.w = w; ya.N = N; ya.K = Kc; ya.kper = kper; ya.nsplit = nsplit;
     ya.part = part; ya.part_stride = part_stride; ya.tiles = nlower;
-    {
+    for (int m = 0; m < npm; ++m) {
+      if (m > 0) {
+        hipLaunchKernelGGL(scale_cols_kernel, dim3(nblocks((long)N * Kc)), dim3(256), 0, st, N,
+                           Kc, kcap, w, Z);
+        AGF2_CHECK_LAUNCH();
+      }
+      ya.part = part + m * pair_stride;
       // algorithmic: lower triangles of two symmetric N x N products over Kc
       ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 1.0) * Kc);
       launch_syrk_f64(ya, st);
     }
     P0 = P1;
   }
-  ProfScope ps(h, "moments.reduce", 0.0, 8.0 * (2.0 * nsplit_max + 2.0) * nn);
-  reduce_moment_partials(part, part_stride, nsplit_max, N, U0, U1, st);
+  ProfScope ps(h, "moments.reduce", 0.0, 8.0 * (2.0 * nsplit_max + 2.0) * nn * npm);
+  for (int m = 0; m < npm; ++m)
+    reduce_moment_partials(part + m * pair_stride, part_stride, nsplit_max, N, U[2 * m],
+                           U[2 * m + 1], st);
 }
 
 // Pole-basis DF tensors, Q padded to Qp (a multiple of 16) with zeros:
@@ -633,9 +658,9 @@ void lov_transform_f64(int N, int Q, int Qp, const double* u, int npole, int o, 
   gemm_f64_padded(g, Qp, st);
 }
 
-void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
-                       int nocc, const double* e, const double* u, double* m0o,
-                       double* m1o, double* m0v, double* m1v) {
+void build_moments_f64_n(Handle& h, int N, int Q, const double* L, int npole, int nocc,
+                         const double* e, const double* u, int npm, double* const* Uo,
+                         double* const* Uv) {
   const int o = nocc, v = npole - nocc;
   const int Qp = (Q + BK - 1) / BK * BK;
   double* Lxo = h.ws_moments[0].as<double>((long)o * N * Qp);
@@ -651,10 +676,18 @@ void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
   }
   // lesser: pairs (i, j) occupied, inner a virtual; S[j][a][Q] = Lov[j][a][Q]
   moments_part_f64(h, N, Q, Qp, Lxo, (long)N * Qp, Qp, Lov, (long)v * Qp, Qp,
-                   e, o, e + o, v, m0o, m1o);
+                   e, o, e + o, v, npm, Uo);
   // greater: pairs (a, b) virtual, inner i occupied; S[b][i][Q] = Lov[i][b][Q]
   moments_part_f64(h, N, Q, Qp, Lxv, (long)N * Qp, Qp, Lov, Qp, (long)v * Qp,
-                   e + o, v, e, o, m0v, m1v);
+                   e + o, v, e, o, npm, Uv);
+}
+
+void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
+                       int nocc, const double* e, const double* u, double* m0o,
+                       double* m1o, double* m0v, double* m1v) {
+  double* const Uo[2] = {m0o, m1o};
+  double* const Uv[2] = {m0v, m1v};
+  build_moments_f64_n(h, N, Q, L, npole, nocc, e, u, 1, Uo, Uv);
 }
 
 }  // namespace agf2

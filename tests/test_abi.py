@@ -52,12 +52,16 @@ def test_null_handle_is_rejected(lib):
 def test_run_state_size(lib):
     """The checkpoint size of agf2_run is a host-side formula: header plus
     the saved arrays (poles, density, previous moments, DIIS history)."""
-    lib.agf2_run_state_bytes.restype = ctypes.c_long
-    lib.agf2_run_state_bytes.argtypes = [ctypes.c_int, ctypes.c_int]
-    n, sp = 24, 8
-    nn = n * n
-    doubles = 3 * n + 3 * nn + nn + 4 * nn + 4 * nn + sp * 2 * 4 * nn + sp * sp
-    b = lib.agf2_run_state_bytes(n, sp)
-    assert 0 < b - 8 * doubles <= 512
-    assert lib.agf2_run_state_bytes(0, 8) == -1
-    assert lib.agf2_run_state_bytes(10, 65) == -1
+    from paper_2106_03508_amd import agf2
+    lib = agf2.load_library()
+    for n, sp, nb in ((24, 8, 1), (30, 3, 2)):
+        nn = n * n
+        npmax = n * (1 + 2 * nb)
+        ln = 4 * nb * nn
+        doubles = npmax + n * npmax + nn + ln + ln + sp * 2 * ln + sp * sp
+        o = agf2.run_opts(diis_space=sp, nblock=nb)
+        b = lib.agf2_run_state_bytes(n, ctypes.byref(o))
+        assert 0 < b - 8 * doubles <= 512
+    assert lib.agf2_run_state_bytes(0, None) == -1
+    assert lib.agf2_run_state_bytes(10, ctypes.byref(agf2.run_opts(diis_space=65))) == -1
+    assert lib.agf2_run_state_bytes(10, ctypes.byref(agf2.run_opts(nblock=0))) == -1

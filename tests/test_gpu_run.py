@@ -163,7 +163,7 @@ def test_agf2_run_state_rejects_mismatch(h):
     with pytest.raises(agf2.Agf2Error) as ei:
         agf2.agf2_run_resume(h, Ld, hc, dev(eps), nocc, agf2.run_opts(diis_space=4),
                              state_in=first["state"][:agf2.load_library().agf2_run_state_bytes(
-                                 24, 4)])
+                                 24, agf2.run_opts(diis_space=4))])
     assert ei.value.status == -1
     junk = np.zeros_like(first["state"])
     with pytest.raises(agf2.Agf2Error) as ei:

@@ -498,3 +498,134 @@ def test_spectral_function_single_pole_is_a_lorentzian():
     ref = 0.36 * 0.05 / np.pi / ((omega - 0.25) ** 2 + 0.05 ** 2)
     assert np.abs(A - ref).max() < 1e-14 * ref.max()
     assert np.argmax(A) == np.argmin(np.abs(omega - 0.25))
+
+
+# ------------------------------------------- higher moments, Lanczos blocks
+
+def test_higher_moments_two_equal_the_first_two():
+    eps, L, nocc = small_system(nmo=10, nocc=3, naux=30)
+    e, u = syn.random_poles(9, 10, 30, 11)
+    ref = O.se_moments(L, e, u, 11)
+    mo, mv = O.se_moments_n(L, e, u, 11, 2)
+    for a, b in zip((mo[0], mo[1], mv[0], mv[1]), ref):
+        assert rel(a, b) < 1e-14
+
+
+def test_higher_moments_equal_uncompressed_auxiliaries():
+    """U(n) = V diag(E^n) V^T with the explicit auxiliaries of the
+    second-order self-energy (a different route: pairs summed as squares)."""
+    eps, L, nocc = small_system(nmo=8, nocc=3, naux=20)
+    e, u = syn.random_poles(3, 8, 20, 7)
+    Eo, Vo, Ev, Vv = O.uncompressed_self_energy(L, e, u, 7)
+    mo, mv = O.se_moments_n(L, e, u, 7, 6)
+    for n in range(6):
+        assert rel(mo[n], (Vo * Eo ** n) @ Vo.T) < 1e-12
+        assert rel(mv[n], (Vv * Ev ** n) @ Vv.T) < 1e-12
+
+
+def test_higher_moments_degenerate_spectrum_closed_form():
+    """All occupied poles at eo, all virtual at ev: every summand of part <
+    carries the weight (2 eo - ev), so U<(n) = (2 eo - ev)^n U<(0), and
+    U>(n) = (2 ev - eo)^n U>(0)."""
+    eps, L, nocc = small_system(nmo=9, nocc=3, naux=25)
+    eo_, ev_ = -0.7, 1.3
+    e = np.array([eo_] * 3 + [ev_] * 6)
+    mo, mv = O.se_moments_n(L, e, np.eye(9), 3, 6)
+    for n in range(6):
+        assert rel(mo[n], (2 * eo_ - ev_) ** n * mo[0]) < 1e-13
+        assert rel(mv[n], (2 * ev_ - eo_) ** n * mv[0]) < 1e-13
+
+
+def test_block_lanczos_one_block_is_the_compression():
+    eps, L, nocc = small_system(nmo=12, nocc=4, naux=40)
+    e, u = syn.random_poles(2, 12, 36, 15)
+    m = O.se_moments(L, e, u, 15)
+    for m0, m1 in ((m[0], m[1]), (m[2], m[3])):
+        e1, v1 = O.compress(m0, m1)
+        e2, v2 = O.block_lanczos([m0, m1])
+        assert np.abs(e1 - e2).max() < 1e-12 * np.abs(e1).max()
+        for w in (-3.0, 0.2, 4.0):
+            assert rel(O.self_energy_at(w, e1, v1), O.self_energy_at(w, e2, v2)) < 1e-12
+
+
+@pytest.mark.parametrize("nblock", [2, 3])
+def test_block_lanczos_conserves_moments(nblock):
+    eps, L, nocc = small_system(nmo=10, nocc=3, naux=40)
+    e, u = syn.random_poles(5, 10, 30, 11)
+    mo, mv = O.se_moments_n(L, e, u, 11, 2 * nblock)
+    for mm in (mo, mv):
+        ea, va = O.block_lanczos(list(mm))
+        assert ea.shape == (nblock * 10,) and va.shape == (10, nblock * 10)
+        for n in range(2 * nblock):
+            assert rel((va * ea ** n) @ va.T, mm[n]) < 1e-10, n
+        # one moment past the conserved ones is not reproduced
+        ref = O.se_moments_n(L, e, u, 11, 2 * nblock + 1)[0 if mm is mo else 1][-1]
+        assert rel((va * ea ** (2 * nblock)) @ va.T, ref) > 1e-6
+
+
+def _explicit_block_lanczos(E, V, nblock):
+    """Block Lanczos run directly on the explicit auxiliary space: H =
+    diag(E), start block Q0 = V^T S^-T, each new block orthogonalised
+    against all earlier ones (full reorthogonalisation) and normalised by a
+    QR factorisation. Returns the block tridiagonal matrix and S."""
+    N = V.shape[0]
+    S = np.linalg.cholesky(V @ V.T)
+    Q = [V.T @ np.linalg.inv(S).T]
+    T = np.zeros((nblock * N, nblock * N))
+    for j in range(nblock):
+        HQ = E[:, None] * Q[j]
+        T[j * N:(j + 1) * N, j * N:(j + 1) * N] = Q[j].T @ HQ
+        if j + 1 == nblock:
+            break
+        R = HQ.copy()
+        for _ in range(2):
+            for q in Q:
+                R -= q @ (q.T @ R)
+        Qn, Bn = np.linalg.qr(R)
+        T[(j + 1) * N:(j + 2) * N, j * N:(j + 1) * N] = Bn
+        T[j * N:(j + 1) * N, (j + 1) * N:(j + 2) * N] = Bn.T
+        Q.append(Qn)
+    return 0.5 * (T + T.T), S
+
+
+@pytest.mark.parametrize("nblock", [2, 3])
+def test_block_lanczos_equals_explicit_lanczos(nblock):
+    """The moment-only recursion gives the same compressed self-energy as
+    block Lanczos run on the explicit auxiliaries of the second-order
+    self-energy (Sigma(w) compared at frequencies off the real poles)."""
+    eps, L, nocc = small_system(nmo=6, nocc=2, naux=18)
+    e, u = syn.random_poles(4, 6, 18, 6)
+    Eo, Vo, Ev, Vv = O.uncompressed_self_energy(L, e, u, 6)
+    mo, mv = O.se_moments_n(L, e, u, 6, 2 * nblock)
+    for (E, V), mm in (((Eo, Vo), mo), ((Ev, Vv), mv)):
+        ea, va = O.block_lanczos(list(mm))
+        T, S = _explicit_block_lanczos(E, V, nblock)
+        N = V.shape[0]
+        for w in (-5.0 + 0.3j, 0.1 + 0.5j, 6.0 - 0.2j):
+            G = np.linalg.inv(w * np.eye(nblock * N) - T)[:N, :N]
+            ref = S @ G @ S.T
+            got = (va / (w - ea)) @ va.T
+            assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_block_lanczos_rejects_non_pd():
+    m0 = np.diag([1.0, 0.0, 2.0])
+    with pytest.raises(O.NotPositiveDefinite):
+        O.block_lanczos([m0, np.eye(3), np.eye(3), np.eye(3)])
+
+
+def test_agf2_more_blocks_converges_with_5n_poles():
+    """AGF2 with two Lanczos blocks per part: N + 4N poles, the electron
+    number kept, and the same kind of fixed point (IP/EA within a few mHa of
+    the one-block run on this weakly correlated system)."""
+    sysd = syn.system(0, **syn.SMALL)
+    eps, L, nocc = sysd["eps"], sysd["L"], sysd["nocc"]
+    h = O.synthetic_hcore(eps, L, nocc)
+    a = O.run_agf2(h, L, eps, nocc, nblock=2)
+    b = O.run_agf2(h, L, eps, nocc)
+    assert a["converged"]
+    last = a["history"][-1]
+    assert last["npole"] == 5 * 24
+    assert abs(np.trace(a["rdm1"]) - 2 * nocc) < 1e-8
+    hb = b["history"][-1]
+    assert abs(last["ip"] - hb["ip"]) < 5e-3 and abs(last["ea"] - hb["ea"]) < 5e-3
