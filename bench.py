@@ -256,6 +256,67 @@ def log(msg):
     print(f"# {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
+class Heartbeat:
+    """Prints a line to stderr every `every` seconds while a long library
+    call blocks (ctypes releases the GIL during the call)."""
+
+    def __init__(self, what, every=20.0):
+        import threading
+        self.what, self.every = what, every
+        self.stop = threading.Event()
+        self.t0 = time.perf_counter()
+        self.thread = threading.Thread(target=self.run, daemon=True)
+
+    def run(self):
+        while not self.stop.wait(self.every):
+            log(f"{self.what} running ({time.perf_counter() - self.t0:.0f}s)")
+
+    def __enter__(self):
+        self.thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self.stop.set()
+        self.thread.join()
+
+
+def steady_state_build(agf2, torch, h, Ld, N, nocc, Q, seed, prec):
+    """One moment build at the shape of every iteration after the first:
+    N + 2N poles (the dressed Green's function after a compression to N
+    auxiliaries per part), N + nocc of them occupied. A seeded random pole
+    set (synthetic.random_poles) stands in for a converged Green's
+    function; the work depends only on the shape."""
+    npole, no = 3 * N, N + nocc
+    e3, u3 = syn.random_poles(seed, N, npole, no)
+    e3d = torch.from_numpy(e3).cuda()
+    u3d = torch.from_numpy(np.ascontiguousarray(u3)).cuda()
+    out = tuple(h.empty(N, N) for _ in range(4))
+    torch.cuda.synchronize()
+    agf2.agf2_profile_enable(h, True)
+    log(f"steady-state moment build: {npole} poles, {no} occupied")
+    t0 = time.perf_counter()
+    with Heartbeat("steady-state moment build"):
+        agf2.agf2_build_moments(h, Ld, e3d, u3d, no, prec=prec, out=out)
+        torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = agf2.agf2_profile_read(h)
+    agf2.agf2_profile_enable(h, False)
+    F = canonical_flops(N, no, npole - no, Q)
+    log(f"steady-state moment build {wall:.1f}s ({F / wall / 1e12:.1f} canonical TFLOP/s)")
+    del out, e3d, u3d
+    torch.cuda.empty_cache()
+    return {
+        "shape": f"nmo={N} naux={Q}, {npole} poles ({no} occupied, {npole - no} virtual)",
+        "moment_build_s": round(wall, 3),
+        "canonical_flops": F,
+        "canonical_tflops": round(F / wall / 1e12, 3),
+        "kernels": {k: {"launches": x["launches"], "ms": round(x["ms"], 3),
+                        "avg_ms": round(x["ms"] / max(1, x["launches"]), 4),
+                        "tflops": round(x["flops"] / max(x["ms"], 1e-9) / 1e9, 3)}
+                    for k, x in sorted(prof.items())},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,14 +326,21 @@ def main():
     ap.add_argument("--prec", default="split_fp16", choices=["fp64", "split_bf16", "split_fp16"])
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-occ-sample", type=int, default=1)
-    ap.add_argument("--cpu-vir-sample", type=int, default=1)
+    ap.add_argument("--cpu-occ-sample", type=int, default=4)
+    ap.add_argument("--cpu-vir-sample", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (a calibration dispatch of "
                          "known size for HBM counters; outside the timed region)")
     ap.add_argument("--batch-poles", default="dressed3n", choices=["hf", "dressed3n"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="batch64: wall time budget of the oracle sample")
+    ap.add_argument("--no-steady", action="store_true",
+                    help="skip the timed moment build at the steady-state (3N-pole) shape")
+    ap.add_argument("--steady-only", action="store_true",
+                    help="only the moment build at the steady-state shape (for profiler runs)")
+    ap.add_argument("--moments-only", action="store_true",
+                    help="time only iteration-0 moment builds, no compression or Fock loop "
+                         "(for profiler runs)")
     ap.add_argument("--converge", action="store_true",
                     help="run AGF2 from the mean-field reference to self-consistency once "
                          "and report the wall time (instead of timed iteration-0 steps)")
@@ -313,9 +381,36 @@ def main():
     log("inputs resident on the GPU")
     if args.converge:
         return main_converge(args, agf2, torch, h, Ld, hcore, epsd, N, nocc, Q)
+    if args.steady_only:
+        st = steady_state_build(agf2, torch, h, Ld, N, nocc, Q, seed, args.prec)
+        print(json.dumps({"metric": "steady-state moment build (canonical TFLOP/s)",
+                          "value": st["canonical_tflops"], "unit": "TFLOP/s", "n_gpus": 1,
+                          "dtype": DTYPES[args.prec], "data": "synthetic",
+                          "config": {"workload": st["shape"], "precision": args.prec},
+                          "steady_state": st}), flush=True)
+        return
     m_out = tuple(h.empty(N, N) for _ in range(4))
     o, v = nocc, N - nocc
     F_canon = canonical_flops(N, o, v, Q)
+    if args.moments_only:
+        for _ in range(args.warmup):
+            agf2.agf2_build_moments(h, Ld, epsd, eye, nocc, prec=args.prec, out=m_out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            agf2.agf2_build_moments(h, Ld, epsd, eye, nocc, prec=args.prec, out=m_out)
+            torch.cuda.synchronize()
+            log(f"moment build {k + 1}/{args.steps}")
+        dt = (time.perf_counter() - t0) / max(1, args.steps)
+        print(json.dumps({"metric": "iteration-0 moment build (canonical TFLOP/s)",
+                          "value": round(F_canon / dt / 1e12, 3), "unit": "TFLOP/s",
+                          "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": round(1e3 * dt, 3), "dtype": DTYPES[args.prec],
+                          "data": "synthetic",
+                          "config": {"workload": f"moment build from the mean-field reference, "
+                                                 f"nmo={N} nocc={nocc} naux={Q}",
+                                     "precision": args.prec}}), flush=True)
+        return
 
     def step(rec):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -393,6 +488,8 @@ def main():
         "traffic_note": None,
         "cpu_baseline": None,
     }
+    if not args.no_steady:
+        out["steady_state"] = steady_state_build(agf2, torch, h, Ld, N, nocc, Q, seed, args.prec)
     tr = measured_traffic(dom, args.prec, args.workload)
     if tr is not None:
         out["roofline"]["traffic"] = tr["bytes_per_launch"]

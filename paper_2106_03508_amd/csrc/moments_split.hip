@@ -19,6 +19,7 @@
 //     fixed order.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "agf2_internal.h"
@@ -446,102 +447,107 @@ struct SyrkArgs {
   int N; long K; long kper;
   double u0scale, u1scale;   // 2^-2fZ, 2^-(fZ+fW)
   double* part; long part_stride;
-  int tiles, nsplit;         // lower-triangle tiles, K splits (grid = tiles * nsplit)
+  int tiles, nsplit, nxt;    // lower-triangle tiles, K splits (grid = tiles * nsplit), x blocks
+  int lolo_all;              // 1: lo*lo products on every sub-tile
 };
 
-constexpr int TS = 64;   // SYRK output tile
+constexpr int SX = 64, SY = 128;   // SYRK output tile: 64 x rows by 128 y rows
+constexpr int SNT = 512;           // eight waves, two per SIMD
 
+// Lower-triangle tiles of U0 += Z Z^T and U1 += (wZ) Z^T from the 16-bit
+// pairs, K split into float64 partials. Tile t is numbered y block major: y
+// block yt (128 rows) holds x blocks (64 rows) 2 yt .. nxt - 1, the x blocks
+// that reach the diagonal or below it. Each wave owns a 32 x 32 sub-tile and
+// both moments; a wave whose sub-tile lies above the diagonal skips its
+// MFMAs. A 64 x 128 tile moves a third fewer operand bytes per output element
+// than a 64 x 64 one.
+// Products: hi*hi into one float32 sum, hi*lo + lo*hi (+ lo*lo) into another;
+// every KC_STEPS steps both are folded into float64. lo*lo is taken only on
+// sub-tiles holding diagonal elements (or on all with lolo_all): there it is
+// a non-negative square that dropping would bias, elsewhere a term of random
+// sign ~2^-22 times the summand (measured: no change of the moment errors).
 template <bool F16>
-__global__ __launch_bounds__(NT, 2) void syrk_split_kernel(SyrkArgs a) {
+__global__ __launch_bounds__(SNT) void syrk_split_kernel(SyrkArgs a) {
   // two stages (double buffer) of: Z hi, Z lo, wZ hi, wZ lo (x rows) and
-  // Z hi, Z lo (y rows); 48 KiB
-  __shared__ u16x8 sX[2][4][TS][KV];
-  __shared__ u16x8 sY[2][2][TS][KV];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // Z hi, Z lo (y rows); 64 KiB
+  __shared__ u16x8 sX[2][4][SX][KV];
+  __shared__ u16x8 sY[2][2][SY][KV];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // (split, tile) work items numbered split-major and dealt to XCDs in
   // contiguous ranges, so the tiles reading one K range share an L2
   const long item = xcd_remap(blockIdx.x, (long)a.tiles * a.nsplit);
   const int t = (int)(item % a.tiles);
-  int xt = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((xt + 1) * (xt + 2) / 2 <= t) ++xt;
-  while (xt * (xt + 1) / 2 > t) --xt;
-  const int yt = t - xt * (xt + 1) / 2;
   const int s = (int)(item / a.tiles);
+  int yt = 0, toff = 0;
+  while (toff + (a.nxt - 2 * yt) <= t) {
+    toff += a.nxt - 2 * yt;
+    ++yt;
+  }
+  const int xt = 2 * yt + (t - toff);
   const long k0 = (long)s * a.kper, k1 = std::min(a.K, k0 + a.kper);
-  if (k1 <= k0) return;
-  const int x0 = xt * TS, y0 = yt * TS;
+  if (k1 <= k0) return;   // uniform over the workgroup
+  const int x0 = xt * SX, y0 = yt * SY;
 
-  // Loader: thread tid moves vector (tid + NT i) of the x operands (4 arrays
-  // x 64 rows x KV vectors) and of the y operands (2 arrays); its global row
-  // pointers and LDS slots are fixed for the whole K range. Rows past N read
-  // row N - 1 instead (they only feed output rows or columns that are not
-  // stored), and a step's 32 columns never pass the row length (a multiple of
-  // 32), so every load is unconditional and in bounds; this keeps the
-  // compiler's count of loads in flight exact across the two register stages.
-  const u16* gx[4];
-  const u16* gy[2];
-  int lx[4], ly[2];
+  // Loader: a step is 2048 16-byte vectors (x: 4 arrays x 64 rows x KV; y: 2
+  // arrays x 128 rows x KV); thread tid moves vectors tid + 512 i, i = 0..3
+  // (i = 0, 1: x arrays 2i, 2i + 1; i = 2, 3: y arrays), with global row
+  // pointers and LDS slots fixed for the whole K range. Rows past N read row
+  // N - 1 (their outputs are not stored) and a step's 32 columns never pass
+  // the row length (a multiple of 32), so every load is unconditional and in
+  // bounds.
+  const u16* gp[4];
+  int lo[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int idx = tid + NT * i;
-    const int arr = idx / (TS * KV), rr = (idx / KV) % TS, kv = idx % KV;
-    const u16* base = arr == 0 ? a.Zh : arr == 1 ? a.Zl : arr == 2 ? a.Wh : a.Wl;
-    gx[i] = base + (long)min(x0 + rr, a.N - 1) * a.ldz + 8 * kv;
-    lx[i] = (arr * TS + rr) * KV + (kv ^ swz(rr));
+    const int idx = tid + SNT * i;
+    const int kv = idx % KV;
+    if (i < 2) {
+      const int arr = idx / (SX * KV), rr = (idx / KV) % SX;
+      const u16* base = arr == 0 ? a.Zh : arr == 1 ? a.Zl : arr == 2 ? a.Wh : a.Wl;
+      gp[i] = base + (long)min(x0 + rr, a.N - 1) * a.ldz + 8 * kv;
+      lo[i] = (arr * SX + rr) * KV + (kv ^ swz(rr));
+    } else {
+      const int j = idx - 2 * SNT;
+      const int arr = j / (SY * KV), rr = (j / KV) % SY;
+      const u16* base = arr == 0 ? a.Zh : a.Zl;
+      gp[i] = base + (long)min(y0 + rr, a.N - 1) * a.ldz + 8 * kv;
+      lo[i] = (arr * SY + rr) * KV + (kv ^ swz(rr));
+    }
   }
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int idx = tid + NT * i;
-    const int arr = idx / (TS * KV), rr = (idx / KV) % TS, kv = idx % KV;
-    const u16* base = arr == 0 ? a.Zh : a.Zl;
-    gy[i] = base + (long)min(y0 + rr, a.N - 1) * a.ldz + 8 * kv;
-    ly[i] = (arr * TS + rr) * KV + (kv ^ swz(rr));
-  }
-  // register stages: the global loads run two k steps ahead of the MFMAs.
-  // Every step issues its six loads with no branch (steps past the end
-  // re-read the last one, unused), so the wait before an LDS store covers
-  // only the older stage; columns >= k1 of the last step are zeroed at store
-  // time.
+  // register stages: the global loads run two k steps ahead of the MFMAs;
+  // steps past the end re-read the last one (unused), columns >= k1 of the
+  // last step are zeroed at store time
   const long nsteps = (k1 - k0 + KS - 1) / KS;
   const long kb_last = k0 + (nsteps - 1) * KS;
-  auto load = [&](long kb, u16x8 (&rx)[4], u16x8 (&ry)[2]) {
+  auto load = [&](long kb, u16x8 (&r)[4]) {
     kb = min(kb, kb_last);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) rx[i] = *reinterpret_cast<const u16x8*>(gx[i] + kb);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) ry[i] = *reinterpret_cast<const u16x8*>(gy[i] + kb);
+    for (int i = 0; i < 4; ++i) r[i] = *reinterpret_cast<const u16x8*>(gp[i] + kb);
   };
-  auto store = [&](int buf, long kb, u16x8 (&rx)[4], u16x8 (&ry)[2]) {
+  auto store = [&](int buf, long kb, u16x8 (&r)[4]) {
     if (kb + KS > k1) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const long k = kb + 8 * ((tid + NT * i) % KV);
+        const long k = kb + 8 * ((tid + SNT * i) % KV);
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-          if (k + e >= k1) rx[i][e] = 0;
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const long k = kb + 8 * ((tid + NT * i) % KV);
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (k + e >= k1) ry[i][e] = 0;
+          if (k + e >= k1) r[i][e] = 0;
       }
     }
     u16x8* bx = &sX[buf][0][0][0];
     u16x8* by = &sY[buf][0][0][0];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bx[lx[i]] = rx[i];
+    for (int i = 0; i < 2; ++i) bx[lo[i]] = r[i];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) by[ly[i]] = ry[i];
+    for (int i = 2; i < 4; ++i) by[lo[i]] = r[i];
   };
 
   const int fr = lane & 15, fk = lane >> 4;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  // hi*hi products and the ~2^-11 smaller cross products (hi*lo, lo*hi,
-  // lo*lo) accumulate separately, so the large sum is rounded once per step;
-  // every KC_STEPS steps both are folded into float64 sums (a few thousand
-  // float64 additions per output element in all, far below the float32 error)
+  const int gx = x0 + wm, gy = y0 + wn;
+  const bool active = gx + 31 >= gy;          // some element on or below the diagonal
+  const bool lolo = a.lolo_all || gx == gy;    // sub-tile holds diagonal elements
   f4 u0[2][2], u1[2][2], v0[2][2], v1[2][2];
   double s0[2][2][4], s1[2][2][4];
   const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
@@ -574,47 +580,51 @@ __global__ __launch_bounds__(NT, 2) void syrk_split_kernel(SyrkArgs a) {
   // Steps run in pairs with no branch around loads or stores; for odd nsteps
   // the last body multiplies the zeroed data of step nsteps (all its columns
   // are >= k1), which adds exact zeros.
-  auto body = [&](long step, int buf, u16x8 (&cx)[4], u16x8 (&cy)[2], u16x8 (&nx)[4],
-                  u16x8 (&ny)[2]) {
-    load(k0 + (step + 2) * KS, cx, cy);
-    u16x8 xh[2], xl[2], wh[2], wl[2], yh[2], yl[2];
+  auto body = [&](long step, int buf, u16x8 (&cur)[4], u16x8 (&nxt)[4]) {
+    load(k0 + (step + 2) * KS, cur);
+    if (active) {
+      u16x8 xh[2], xl[2], wh[2], wl[2], yh[2], yl[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int rx_ = wm + 16 * i + fr, ry_ = wn + 16 * i + fr;
-      const int sx = fk ^ swz(rx_), sy = fk ^ swz(ry_);
-      xh[i] = sX[buf][0][rx_][sx];
-      xl[i] = sX[buf][1][rx_][sx];
-      wh[i] = sX[buf][2][rx_][sx];
-      wl[i] = sX[buf][3][rx_][sx];
-      yh[i] = sY[buf][0][ry_][sy];
-      yl[i] = sY[buf][1][ry_][sy];
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        u0[i][j] = mfma<F16>(xh[i], yh[j], u0[i][j]);
-        v0[i][j] = mfma<F16>(xh[i], yl[j], v0[i][j]);
-        v0[i][j] = mfma<F16>(xl[i], yh[j], v0[i][j]);
-        v0[i][j] = mfma<F16>(xl[i], yl[j], v0[i][j]);
-        u1[i][j] = mfma<F16>(wh[i], yh[j], u1[i][j]);
-        v1[i][j] = mfma<F16>(wh[i], yl[j], v1[i][j]);
-        v1[i][j] = mfma<F16>(wl[i], yh[j], v1[i][j]);
-        v1[i][j] = mfma<F16>(wl[i], yl[j], v1[i][j]);
+      for (int i = 0; i < 2; ++i) {
+        const int rx_ = wm + 16 * i + fr, ry_ = wn + 16 * i + fr;
+        const int sx = fk ^ swz(rx_), sy = fk ^ swz(ry_);
+        xh[i] = sX[buf][0][rx_][sx];
+        xl[i] = sX[buf][1][rx_][sx];
+        wh[i] = sX[buf][2][rx_][sx];
+        wl[i] = sX[buf][3][rx_][sx];
+        yh[i] = sY[buf][0][ry_][sy];
+        yl[i] = sY[buf][1][ry_][sy];
       }
-    if ((step + 1) % KC_STEPS == 0) flush();
-    store(buf ^ 1, k0 + (step + 1) * KS, nx, ny);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          u0[i][j] = mfma<F16>(xh[i], yh[j], u0[i][j]);
+          v0[i][j] = mfma<F16>(xh[i], yl[j], v0[i][j]);
+          v0[i][j] = mfma<F16>(xl[i], yh[j], v0[i][j]);
+          u1[i][j] = mfma<F16>(wh[i], yh[j], u1[i][j]);
+          v1[i][j] = mfma<F16>(wh[i], yl[j], v1[i][j]);
+          v1[i][j] = mfma<F16>(wl[i], yh[j], v1[i][j]);
+          if (lolo) {
+            v0[i][j] = mfma<F16>(xl[i], yl[j], v0[i][j]);
+            v1[i][j] = mfma<F16>(wl[i], yl[j], v1[i][j]);
+          }
+        }
+      if ((step + 1) % KC_STEPS == 0) flush();
+    }
+    store(buf ^ 1, k0 + (step + 1) * KS, nxt);
     __syncthreads();
   };
-  u16x8 ax[4], ay[2], bx[4], by[2];
-  load(k0, ax, ay);
-  load(k0 + KS, bx, by);
-  store(0, k0, ax, ay);
+  u16x8 ra[4], rb[4];
+  load(k0, ra);
+  load(k0 + KS, rb);
+  store(0, k0, ra);
   __syncthreads();
   for (long step = 0; step < nsteps; step += 2) {
-    body(step, 0, ax, ay, bx, by);
-    body(step + 1, 1, bx, by, ax, ay);
+    body(step, 0, ra, rb);
+    body(step + 1, 1, rb, ra);
   }
+  if (!active) return;
   flush();
 
   double* P0 = a.part + (long)s * a.part_stride;
@@ -625,9 +635,9 @@ __global__ __launch_bounds__(NT, 2) void syrk_split_kernel(SyrkArgs a) {
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int x = x0 + wm + 16 * i + crow(lane, r);
-        const int y = y0 + wn + 16 * j + fr;
-        if (x >= a.N || y >= a.N) continue;
+        const int x = gx + 16 * i + crow(lane, r);
+        const int y = gy + 16 * j + fr;
+        if (x >= a.N || y > x) continue;
         const long o = (long)x * a.N + y;
         P0[o] += s0[i][j][r];
         P1[o] += s1[i][j][r];
@@ -679,6 +689,18 @@ int exponent_above(double x) {
   return e;
 }
 
+// 1 when AGF2_SYRK_LOLO_ALL=1 is set in the environment: lo*lo products on
+// every contraction sub-tile instead of the diagonal ones only (a precision
+// check of the default)
+int lolo_all() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("AGF2_SYRK_LOLO_ALL");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v;
+}
+
 struct PartScales {
   const int* eR = nullptr;
   const int* eS = nullptr;
@@ -692,12 +714,12 @@ struct PartScales {
 // Workgroups resident on the whole device for a kernel (compute units x
 // resident workgroups per unit), queried once per kernel.
 template <class K>
-int device_slots(K kernel, int& cache) {
+int device_slots(K kernel, int& cache, int threads = NT) {
   if (cache > 0) return cache;
   int dev = 0, cus = 0, per = 0;
   AGF2_HIP(hipGetDevice(&dev));
   AGF2_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  AGF2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, NT, 0));
+  AGF2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0));
   cache = std::max(1, cus) * std::max(1, per);
   return cache;
 }
@@ -773,9 +795,11 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
   const long xel = (long)kb * N * (long)kb * nc;
   float* X = reinterpret_cast<float*>(h.ws_moments[3].as<double>(CB * xel + 8));
 
-  const int tiles_n = (N + TS - 1) / TS;
-  const int nlower = tiles_n * (tiles_n + 1) / 2;
-  const int nsplit_max = std::max(1, std::min(64, (2048 + nlower - 1) / nlower));
+  const int nxt = (N + SX - 1) / SX, nyt = (N + SY - 1) / SY;
+  int ntiles = 0;
+  for (int yt = 0; yt < nyt; ++yt) ntiles += std::max(0, nxt - 2 * yt);
+  const int slots = device_slots(syrk_split_kernel<F16>, syrk_slots, SNT);
+  const int nsplit_max = std::max(1, std::min(64, (8 * slots + ntiles - 1) / ntiles));
   const long part_stride = 2 * nn;
   double* part = h.ws_moments[5].as<double>(part_stride * nsplit_max);
   AGF2_HIP(hipMemsetAsync(part, 0, part_stride * nsplit_max * sizeof(double), st));
@@ -866,8 +890,7 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
         }
         AGF2_CHECK_LAUNCH();
       }
-      int nsplit = choose_splits(Kc, nlower, nsplit_max,
-                                 device_slots(syrk_split_kernel<F16>, syrk_slots));
+      int nsplit = choose_splits(Kc, ntiles, nsplit_max, slots);
       long kper = (Kc + nsplit - 1) / nsplit;
       kper = (kper + KS - 1) / KS * KS;
       nsplit = (int)((Kc + kper - 1) / kper);
@@ -878,9 +901,10 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
       ya.part = part; ya.part_stride = part_stride;
       {
         ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 0.0) * Kc);
-        ya.tiles = nlower; ya.nsplit = nsplit;
-        hipLaunchKernelGGL((syrk_split_kernel<F16>), dim3((unsigned)(nlower * nsplit)), dim3(NT),
-                           0, st, ya);
+        ya.tiles = ntiles; ya.nsplit = nsplit; ya.nxt = nxt;
+        ya.lolo_all = lolo_all();
+        hipLaunchKernelGGL((syrk_split_kernel<F16>), dim3((unsigned)(ntiles * nsplit)),
+                           dim3(SNT), 0, st, ya);
         AGF2_CHECK_LAUNCH();
       }
     }

@@ -1,13 +1,18 @@
 """Split-precision moment builds against the FP64 oracle.
 
-split_fp16 (fp16 hi/lo pairs with power-of-two scaling, 22 significant bits
-per operand, float32 accumulation) meets the reduced-precision bar of 1e-7
-relative Frobenius on every moment at the double-zeta-like size (nmo=200) and
-above; on the tiny cases, where only a few hundred terms are summed, the
-float32 accumulation and operand rounding leave up to ~1.5e-7, so those are
-held to 2e-7. split_bf16 (bf16 hi/lo pairs, 16 significant bits) carries
-~2^-16 error per integral and is held to 1.5e-5; the measured errors are
-printed."""
+split_fp16 (fp16 hi/lo pairs with power-of-two scaling: 22 significant bits
+per operand, float32 accumulation) is held to the reduced-precision bar of
+1e-7 relative Frobenius on every moment, with one exception: the single
+occupied pole case, whose lesser moments sum only 19 Z columns. There the
+operands' own 22-bit rounding (relative error up to 2^-22 per operand) does
+not average out; a CPU emulation of the scheme with exact operands and the
+same float32 accumulation reaches 4e-8 where the scheme gives 1.2e-7, so the
+floor is the representation, not the kernels. That case is held to 2e-7 and
+does not meet the bar.
+
+split_bf16 (bf16 hi/lo pairs, 16 significant bits) carries ~2^-16 error per
+operand and does not meet the 1e-7 bar at any size (measured 1e-6 - 1e-5);
+it is held to its own bound of 1.5e-5 and the errors are printed."""
 import numpy as np
 import pytest
 import torch
@@ -17,8 +22,9 @@ from paper_2106_03508_amd import synthetic as syn
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"split_fp16": 2e-7, "split_bf16": 1.5e-5}
-TOL_MEDIUM = {"split_fp16": 1e-7, "split_bf16": 1.5e-5}
+TOL = {"split_fp16": 1e-7, "split_bf16": 1.5e-5}
+# the few-term case below the bar (see the module docstring)
+TOL_FEW_TERMS = {"split_fp16": 2e-7, "split_bf16": 1.5e-5}
 
 
 @pytest.fixture(scope="module")
@@ -81,7 +87,7 @@ def test_moments_split_match_oracle(h, name, nmo, naux, poles, prec):
     print(name, prec, "rel err", [f"{x:.2e}" for x in errs], flush=True)
     for g in got:
         assert np.array_equal(g, g.T)
-    assert max(errs) < (TOL_MEDIUM if nmo >= 200 else TOL)[prec]
+    assert max(errs) < (TOL_FEW_TERMS if name == "single_occ" else TOL)[prec]
 
 
 @pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
