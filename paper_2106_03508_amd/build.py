@@ -67,5 +67,47 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
     return LIB
 
 
+ASAN_EXE = os.path.join(HERE, "agf2_asan_check")
+# host code only: each sanitizer flag applies to the host compilation
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_asan_check(verbose: bool = True, jobs: int | None = None) -> str:
+    """The library's sources and tests/asan_driver.cpp with the host code
+    built under AddressSanitizer and UndefinedBehaviorSanitizer, linked into
+    one executable (a check of the host paths of the C ABI; run on a GPU)."""
+    srcs = sources() + [os.path.join(ROOT, "tests", "asan_driver.cpp")]
+    odir = os.path.join(OBJ, "asan")
+    os.makedirs(odir, exist_ok=True)
+    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(ROCM, "include")]
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"] + ["-O1", "-g"] + SANITIZE
+    objs = [os.path.join(odir, os.path.basename(s).rsplit(".", 1)[0] + ".o") for s in srcs]
+    cmds = []
+    for s, o in zip(srcs, objs):
+        lang = ["-x", "hip"] if s.endswith(".cpp") else []
+        cmds.append([HIPCC] + flags + inc + ["-c"] + lang + [s, "-o", o])
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_run, cmds))
+    for s, (rc, msg) in zip(srcs, results):
+        if rc != 0:
+            sys.stderr.write(f"--- {os.path.basename(s)}\n{msg}\n")
+            raise RuntimeError("hipcc failed to compile the sanitizer check")
+    tmp = ASAN_EXE + ".tmp"
+    link = ([HIPCC, "--offload-arch=gfx950"] + SANITIZE + objs +
+            ["-o", tmp, "-L" + os.path.join(ROCM, "lib"), "-lrocsolver", "-lrocblas",
+             "-Wl,-rpath," + os.path.join(ROCM, "lib")])
+    rc, msg = _run(link)
+    if rc != 0:
+        sys.stderr.write(msg + "\n")
+        raise RuntimeError("hipcc failed to link the sanitizer check")
+    os.replace(tmp, ASAN_EXE)
+    if verbose:
+        print(f"built {ASAN_EXE}", flush=True)
+    return ASAN_EXE
+
+
 if __name__ == "__main__":
     build()
+    build_asan_check()

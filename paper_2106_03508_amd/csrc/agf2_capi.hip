@@ -548,6 +548,10 @@ struct FockLoop {
   const double* L; const double* e; const double* v;
   double nelec;
   double* H; double* lam; double* work; int* info; double* w;
+  // host copies of the eigenvalues and pole weights of the last solve, in a
+  // buffer of the loop's own (not the handle's shared scratch, which other
+  // calls may reallocate)
+  std::vector<double> hbuf;
   double* hlam; double* hw;
   double solved_shift = NAN;
   const double* solved_F = nullptr;
@@ -562,8 +566,8 @@ struct FockLoop {
     work = lam + n;
     w = lam + 2L * n;
     info = reinterpret_cast<int*>(lam + 3L * n);
-    double* hs = host_scratch(h, 2L * n + 4096);
-    hlam = hs + 4096;
+    hbuf.assign(2L * n, 0.0);
+    hlam = hbuf.data();
     hw = hlam + n;
   }
 
