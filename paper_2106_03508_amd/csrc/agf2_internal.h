@@ -53,28 +53,24 @@ struct Handle;
 // D[l / 16 + 4 r][l % 16].
 
 // ---------------------------------------------------------------- GEMM
-// C[b][s][m][n] = alpha * sum_{r in split s} sum_k A(b,r,m,k) B(b,r,k,n)
-//               + beta * C[b][s][m][n]
-// Addresses: A + b*sAb + r*sAr + m*sAm + k*sAk (likewise B and C). The reduce
-// index r runs over [0, R) and is divided into `nsplit` contiguous ranges, one
-// per output slice s (slice stride sCs). Either sAm or sAk must be 1, and
-// either sBn or sBk must be 1 (the contiguous one is used for coalescing).
+// C[b][m][n] = alpha * sum_k A(b,m,k) B(b,k,n) + beta * C[b][m][n]
+// Addresses: A + b*sAb + m*sAm + k*sAk (likewise B and C). Either sAm or sAk
+// must be 1, and either sBn or sBk must be 1 (the contiguous one is used for
+// coalescing); C is written with lanes along n, so sCn = 1 coalesces.
 struct Gemm {
   int M = 0, N = 0, K = 0;
-  int batch = 1, R = 1, nsplit = 1;
+  int batch = 1;
   const double* A = nullptr;
-  long sAb = 0, sAr = 0, sAm = 0, sAk = 0;
+  long sAb = 0, sAm = 0, sAk = 0;
   const double* B = nullptr;
-  long sBb = 0, sBr = 0, sBk = 0, sBn = 0;
+  long sBb = 0, sBk = 0, sBn = 0;
   double* C = nullptr;
-  long sCb = 0, sCs = 0, sCm = 0, sCn = 0;
+  long sCb = 0, sCm = 0, sCn = 0;
   double alpha = 1.0, beta = 0.0;
   bool lower = false;   // square outputs: only tiles on or below the diagonal are written
 };
 void gemm_f64(const Gemm& g, hipStream_t stream);
 void gemm_f64_padded(const Gemm& g, int Npad, hipStream_t stream);
-int gemm_f64_slots();               // resident GEMM workgroups on the device
-int gemm_f64_tiles(int M, int N);   // output tiles of an M x N product
 
 // Sum `nslice` [rows][cols] slices spaced `slice_stride` apart into out
 // (fixed order), optionally scaling: out = scale * sum_s in[s] (+ out if add).
@@ -122,13 +118,6 @@ void pole_transform_f64(int N, int Q, int Qp, const double* L, const double* u, 
                         int p0, int np, double* T, hipStream_t st);
 void lov_transform_f64(int N, int Q, int Qp, const double* u, int npole, int o, int v,
                        const double* Lxv, double* Lov, hipStream_t st);
-// Library-GEMM versions on the handle's stream (not for graph capture).
-// Lov part: a in [0, na) of a chunk Txv[a][x][Qp] (stride sTa per a) into
-// Tov[i][a][Qp] with row stride na * Qp.
-void pole_transform_blas(Handle& h, int N, int Q, int Qp, const double* L, const double* u,
-                         int npole, int p0, int np, double* T);
-void lov_transform_blas(Handle& h, int N, int Q, int Qp, const double* u, int npole, int o,
-                        int na, const double* Txv, long sTa, double* Tov);
 void build_moments_f64(Handle& h, int N, int Q, const double* L, int npole,
                        int nocc, const double* e, const double* u, double* m0o,
                        double* m1o, double* m0v, double* m1v);

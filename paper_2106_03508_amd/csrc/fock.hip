@@ -281,13 +281,14 @@ void exchange_lower(Handle& h, int N, int Q, int QC, const double* L, const doub
   fill_zero(Kp, (long)nsplit * nn, st);
   for (int q0 = 0; q0 < Q; q0 += QC) {
     const int qn = std::min(QC, Q - q0);
-    const double one = 1.0, zero = 0.0;
-    // one GEMM D [L_Q ...] over the chunk (column-major view)
-    const rocblas_status bs =
-        rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none, N, qn * N, N, &one,
-                      D, N, L + (long)q0 * nn, N, &zero, X, N);
-    if (bs != rocblas_status_success)
-      throw Error{AGF2_ERR_HIP, std::string("rocblas_dgemm: ") + rocblas_status_to_string(bs)};
+    // one GEMM over the chunk, X_Q = L_Q D for its slices stacked as rows:
+    // X[n][m] = sum_k L[q0 N^2 + n N + k] D[k N + m], n over qn N rows
+    Gemm g;
+    g.M = qn * N; g.N = N; g.K = N;
+    g.A = L + (long)q0 * nn; g.sAm = N; g.sAk = 1;
+    g.B = D; g.sBk = N; g.sBn = 1;
+    g.C = X; g.sCm = N; g.sCn = 1;
+    gemm_f64(g, st);
     hipLaunchKernelGGL(rho_kernel, dim3(qn), dim3(RT), 0, st, X, N, rho + q0);
     AGF2_CHECK_LAUNCH();
     ExchLower a;

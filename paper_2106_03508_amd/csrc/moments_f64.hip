@@ -352,27 +352,6 @@ __global__ void fill_zero_kernel(double* p, long n) {
 
 inline long nblocks(long n) { return std::max<long>(1, std::min<long>((n + 255) / 256, 4096)); }
 
-// Zero columns [Q, Qp) of `rows` rows of length Qp (the padding the library
-// GEMMs leave unwritten).
-__global__ void zero_pad_kernel(double* T, long rows, int Q, int Qp) {
-  const int w = Qp - Q;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * w;
-       i += (long)gridDim.x * blockDim.x)
-    T[(i / w) * Qp + Q + i % w] = 0.0;
-}
-
-void zero_pad(double* T, long rows, int Q, int Qp, hipStream_t st) {
-  if (Qp == Q || rows == 0) return;
-  hipLaunchKernelGGL(zero_pad_kernel, dim3(nblocks(rows * (Qp - Q))), dim3(256), 0, st, T,
-                     rows, Q, Qp);
-  AGF2_CHECK_LAUNCH();
-}
-
-void blas_check(rocblas_status bs, const char* what) {
-  if (bs != rocblas_status_success)
-    throw Error{AGF2_ERR_HIP, std::string(what) + ": " + rocblas_status_to_string(bs)};
-}
-
 }  // namespace
 
 // Inner tile width for nc inner poles: the width whose padded tiles cost least,
@@ -599,53 +578,6 @@ void pole_transform_f64(int N, int Q, int Qp, const double* L, const double* u, 
   gemm_f64_padded(g, Qp, st);
 }
 
-// The same two transforms as strided-batched library GEMMs on the handle's
-// stream (column-major views; one GEMM per x, resp. per a):
-//   T[p][x][0:Q] = L[0:Q][x][:] u[:][p0+p]          m = Q, n = np, k = N
-//   Lov[i][a][0:Q] = Lxv[a][:][0:Q]^T u[:][i]         m = Q, n = o, k = N
-// with the padding columns [Q, Qp) zeroed. Each call is cut so that no
-// operand of one GEMM spans more than 2 GiB (ld x columns), which keeps every
-// in-matrix byte offset in 31 bits; the cuts are multiples of 128 rows and 64
-// columns where the bound allows.
-namespace {
-int cut(long per_unit_bytes, int total, int align) {
-  const long lim = (1L << 31) / std::max<long>(1, per_unit_bytes);
-  long c = lim >= align ? lim / align * align : std::max<long>(1, lim);
-  return (int)std::min<long>(total, c);
-}
-}  // namespace
-
-void pole_transform_blas(Handle& h, int N, int Q, int Qp, const double* L, const double* u,
-                         int npole, int p0, int np, double* T) {
-  if (np == 0) return;
-  const double one = 1.0, zero = 0.0;
-  const long nn = (long)N * N, ldc = (long)N * Qp;
-  const int qc = cut(8 * nn, Q, 128), pcut = cut(8 * ldc, np, 64);
-  for (int q0 = 0; q0 < Q; q0 += qc)
-    for (int c0 = 0; c0 < np; c0 += pcut)
-      blas_check(rocblas_dgemm_strided_batched(
-                     h.blas, rocblas_operation_transpose, rocblas_operation_transpose,
-                     std::min(qc, Q - q0), std::min(pcut, np - c0), N, &one, L + q0 * nn, nn,
-                     N, u + p0 + c0, npole, 0, &zero, T + c0 * ldc + q0, ldc, Qp, N),
-                 "rocblas_dgemm_strided_batched (pole transform)");
-  zero_pad(T, (long)np * N, Q, Qp, h.stream);
-}
-
-void lov_transform_blas(Handle& h, int N, int Q, int Qp, const double* u, int npole, int o,
-                        int na, const double* Txv, long sTa, double* Tov) {
-  if (o == 0 || na == 0) return;
-  const double one = 1.0, zero = 0.0;
-  const long ldc = (long)na * Qp;
-  const int icut = cut(8 * ldc, o, 64);
-  for (int i0 = 0; i0 < o; i0 += icut)
-    blas_check(rocblas_dgemm_strided_batched(
-                   h.blas, rocblas_operation_none, rocblas_operation_transpose, Q,
-                   std::min(icut, o - i0), N, &one, Txv, Qp, sTa, u + i0, npole, 0, &zero,
-                   Tov + i0 * ldc, ldc, Qp, na),
-               "rocblas_dgemm_strided_batched (Lov transform)");
-  zero_pad(Tov, (long)o * na, Q, Qp, h.stream);
-}
-
 // Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q]
 void lov_transform_f64(int N, int Q, int Qp, const double* u, int npole, int o, int v,
                        const double* Lxv, double* Lov, hipStream_t st) {
@@ -670,9 +602,9 @@ void build_moments_f64_n(Handle& h, int N, int Q, const double* L, int npole, in
     ProfScope ps(h, "moments.transform",
                  2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
                  8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
-    pole_transform_blas(h, N, Q, Qp, L, u, npole, 0, o, Lxo);
-    pole_transform_blas(h, N, Q, Qp, L, u, npole, o, v, Lxv);
-    lov_transform_blas(h, N, Q, Qp, u, npole, o, v, Lxv, (long)N * Qp, Lov);
+    pole_transform_f64(N, Q, Qp, L, u, npole, 0, o, Lxo, h.stream);
+    pole_transform_f64(N, Q, Qp, L, u, npole, o, v, Lxv, h.stream);
+    lov_transform_f64(N, Q, Qp, u, npole, o, v, Lxv, Lov, h.stream);
   }
   // lesser: pairs (i, j) occupied, inner a virtual; S[j][a][Q] = Lov[j][a][Q]
   moments_part_f64(h, N, Q, Qp, Lxo, (long)N * Qp, Qp, Lov, (long)v * Qp, Qp,
