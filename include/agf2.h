@@ -58,14 +58,22 @@ typedef enum {
 /* Arithmetic of the moment build. In both split modes the pole-basis DF
  * tensors are formed in float64, rounded to float32 and stored as 16-bit
  * pairs x ~ hi + lo; the integral slabs take the products hi*hi + hi*lo +
- * lo*hi on the 16-bit MFMA pipe with float32 accumulation, the moment
- * contraction takes all four products (hi*hi and the cross products in
- * separate float32 sums), and those float32 sums over chunks of 256 columns
- * are added into float64 sums. Compression, the Fock loop and the energy are
- * float64 in every mode. */
+ * lo*hi on the 16-bit MFMA pipe with float32 accumulation; the moment
+ * contraction takes hi*hi into one float32 sum and hi*lo + lo*hi into
+ * another (plus lo*lo on output blocks that hold diagonal elements, where
+ * that term is a non-negative square), and those float32 sums over chunks of
+ * 256 columns are added into float64 sums. Compression, the Fock loop and the
+ * energy are float64 in every mode.
+ * Accuracy of the moments against the float64 build (relative Frobenius
+ * norm): fp16 pairs within 1e-7, except on tiny systems whose moment
+ * elements sum only a few terms (up to ~2e-7 with a single occupied pole:
+ * the 2^-22 operand rounding does not average out); bf16 pairs do NOT reach
+ * 1e-7 (about 3e-6 at nphys = 1000, up to ~1e-5 on small systems), because
+ * each bf16 pair holds only 16 significant bits of an operand. */
 typedef enum {
   AGF2_FP64 = 0,        /* float64 operands, FP64 MFMA, float64 accumulation  */
-  AGF2_SPLIT_BF16 = 1,  /* bf16 pairs (16 significant bits per value)         */
+  AGF2_SPLIT_BF16 = 1,  /* bf16 pairs (16 significant bits per value); below
+                           the 1e-7 moment accuracy of the other modes        */
   AGF2_SPLIT_FP16 = 2   /* fp16 pairs (22 significant bits) with power-of-two
                            scaling of each operand row and of the slabs       */
 } agf2_precision;

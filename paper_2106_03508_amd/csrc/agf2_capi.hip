@@ -50,6 +50,33 @@ ProfScope::ProfScope(Handle& hh, const char* name, double flops, double bytes)
   AGF2_HIP(hipEventRecord(rec.start, h.stream));
 }
 
+// Folds the pending records into the totals once their stop events have
+// completed (stream order: the last one's completion implies all). Errors
+// are not thrown from here (it also runs in a destructor): a record whose
+// time cannot be read is dropped.
+static hipError_t prof_drain(Handle& h) noexcept {
+  if (h.prof_pending.empty()) return hipSuccess;
+  const hipError_t sync = hipEventSynchronize(h.prof_pending.back().stop);
+  for (auto& r : h.prof_pending) {
+    float ms = 0.f;
+    if (sync == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+      ProfTotal& t = h.prof_total[r.name];
+      t.launches += 1;
+      t.ms += ms;
+      t.flops += r.flops;
+      t.bytes += r.bytes;
+    }
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  h.prof_pending.clear();
+  return sync;
+}
+
+// At most this many timed launches hold their two events at once; a longer
+// run folds the completed ones (one wait on the last stop event).
+constexpr size_t PROF_PENDING_MAX = 2048;
+
 ProfScope::~ProfScope() {
   if (!on) return;
   if (hipEventRecord(rec.stop, h.stream) != hipSuccess) {
@@ -58,23 +85,11 @@ ProfScope::~ProfScope() {
     return;
   }
   h.prof_pending.push_back(rec);
+  if (h.prof_pending.size() >= PROF_PENDING_MAX) (void)prof_drain(h);
 }
 
 static void prof_flush(Handle& h) {
-  if (h.prof_pending.empty()) return;
-  AGF2_HIP(hipStreamSynchronize(h.stream));
-  for (auto& r : h.prof_pending) {
-    float ms = 0.f;
-    AGF2_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
-    ProfTotal& t = h.prof_total[r.name];
-    t.launches += 1;
-    t.ms += ms;
-    t.flops += r.flops;
-    t.bytes += r.bytes;
-    (void)hipEventDestroy(r.start);
-    (void)hipEventDestroy(r.stop);
-  }
-  h.prof_pending.clear();
+  AGF2_HIP(prof_drain(h));
 }
 
 // One bit of *flag per array: set when any element is NaN or infinite (a
