@@ -315,8 +315,15 @@ struct PairArgs {
   const int* eR; const int* eS; long sEp, sEc;
   float zscale, wscale;
   const double* ep; const double* ec;
-  u16* Zh; u16* Zl; u16* Wh; u16* Wl; long ldz;
+  u16* Zh; u16* Zl; u16* Wh; u16* Wl; long zblk;
 };
+
+// The Z arrays (Z and wZ, hi and lo) are stored K-blocked: column k of row x
+// sits at (k / KS) zblk + x KS + k % KS with zblk = KS N, so the KS columns of
+// a run of rows that one SYRK step reads are one contiguous block.
+__device__ __forceinline__ long zaddr(long zblk, int x, long k) {
+  return (k / KS) * zblk + (long)x * KS + (k % KS);
+}
 
 // Z column values of one (pair, x, c): the P column sqrt(1/2)(x1 + x2) and
 // the M column sqrt(3/2)(x1 - x2) (only x1 for p = q), each with its weighted
@@ -349,8 +356,8 @@ __device__ __forceinline__ void pair_values(float x1, float x2, bool diag, float
 // pole ranges, where the per-pair table fill is amortised over fewer rows,
 // else 4); with V = 2 an element
 // is two adjacent inner poles c, c+1 (nc even: the slab reads are 8-byte and
-// the Z stores 4-byte aligned, since pair column offsets are multiples of nc
-// and Z rows are multiples of 32 long).
+// the Z stores 4-byte aligned, since pair column offsets are multiples of nc,
+// so both columns of an element fall in one K block).
 template <bool F16, int V, int PU>
 __global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
   const long logical = xcd_remap(blockIdx.x, (long)gridDim.x);
@@ -406,7 +413,8 @@ __global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
     const int e = e0 + 256 * u;
     if (e >= per) continue;
     const int x = e / ncv, c = V * (e - x * ncv);
-    const long o = (long)x * a.ldz + colbase + c;
+    const long o = zaddr(a.zblk, x, colbase + c);          // P column
+    const long om = zaddr(a.zblk, x, colbase + a.nc + c);  // M column
     u16 v[V][8];
 #pragma unroll
     for (int t = 0; t < V; ++t) {
@@ -424,11 +432,11 @@ __global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
       if constexpr (V == 2) {
         *reinterpret_cast<unsigned*>(dst[k] + o) = (unsigned)v[0][k] | ((unsigned)v[1][k] << 16);
         if (!diag)
-          *reinterpret_cast<unsigned*>(dst[k] + o + a.nc) =
+          *reinterpret_cast<unsigned*>(dst[k] + om) =
               (unsigned)v[0][4 + k] | ((unsigned)v[1][4 + k] << 16);
       } else {
         dst[k][o] = v[0][k];
-        if (!diag) dst[k][o + a.nc] = v[0][4 + k];
+        if (!diag) dst[k][om] = v[0][4 + k];
       }
     }
   }
@@ -443,7 +451,7 @@ __global__ void transpose_int_kernel(int o, int v, const int* in, int* out) {
 }
 
 struct SyrkArgs {
-  const u16* Zh; const u16* Zl; const u16* Wh; const u16* Wl; long ldz;
+  const u16* Zh; const u16* Zl; const u16* Wh; const u16* Wl; long zblk;  // K-blocked
   int N; long K; long kper;
   double u0scale, u1scale;   // 2^-2fZ, 2^-(fZ+fW)
   double* part; long part_stride;
@@ -492,10 +500,11 @@ __global__ __launch_bounds__(SNT) void syrk_split_kernel(SyrkArgs a) {
   // Loader: a step is 2048 16-byte vectors (x: 4 arrays x 64 rows x KV; y: 2
   // arrays x 128 rows x KV); thread tid moves vectors tid + 512 i, i = 0..3
   // (i = 0, 1: x arrays 2i, 2i + 1; i = 2, 3: y arrays), with global row
-  // pointers and LDS slots fixed for the whole K range. Rows past N read row
-  // N - 1 (their outputs are not stored) and a step's 32 columns never pass
-  // the row length (a multiple of 32), so every load is unconditional and in
-  // bounds.
+  // pointers and LDS slots fixed for the whole K range. A step reads one K
+  // block (the K range starts on a block boundary), in which the tile's rows
+  // are contiguous: 64 or 128 rows of 64 bytes. Rows past N read row N - 1
+  // (their outputs are not stored) and the blocks read lie below kcap, so
+  // every load is unconditional and in bounds.
   const u16* gp[4];
   int lo[4];
 #pragma unroll
@@ -505,13 +514,13 @@ __global__ __launch_bounds__(SNT) void syrk_split_kernel(SyrkArgs a) {
     if (i < 2) {
       const int arr = idx / (SX * KV), rr = (idx / KV) % SX;
       const u16* base = arr == 0 ? a.Zh : arr == 1 ? a.Zl : arr == 2 ? a.Wh : a.Wl;
-      gp[i] = base + (long)min(x0 + rr, a.N - 1) * a.ldz + 8 * kv;
+      gp[i] = base + (long)min(x0 + rr, a.N - 1) * KS + 8 * kv;
       lo[i] = (arr * SX + rr) * KV + (kv ^ swz(rr));
     } else {
       const int j = idx - 2 * SNT;
       const int arr = j / (SY * KV), rr = (j / KV) % SY;
       const u16* base = arr == 0 ? a.Zh : a.Zl;
-      gp[i] = base + (long)min(y0 + rr, a.N - 1) * a.ldz + 8 * kv;
+      gp[i] = base + (long)min(y0 + rr, a.N - 1) * KS + 8 * kv;
       lo[i] = (arr * SY + rr) * KV + (kv ^ swz(rr));
     }
   }
@@ -523,7 +532,7 @@ __global__ __launch_bounds__(SNT) void syrk_split_kernel(SyrkArgs a) {
   auto load = [&](long kb, u16x8 (&r)[4]) {
     kb = min(kb, kb_last);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) r[i] = *reinterpret_cast<const u16x8*>(gp[i] + kb);
+    for (int i = 0; i < 4; ++i) r[i] = *reinterpret_cast<const u16x8*>(gp[i] + (kb / KS) * a.zblk);
   };
   auto store = [&](int buf, long kb, u16x8 (&r)[4]) {
     if (kb + KS > k1) {
@@ -872,7 +881,7 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
       pa.eR = sc.eR; pa.eS = sc.eS; pa.sEp = sc.sEp; pa.sEc = sc.sEc;
       pa.zscale = sc.zscale; pa.wscale = sc.wscale;
       pa.ep = ep; pa.ec = ec;
-      pa.Zh = Zh; pa.Zl = Zl; pa.Wh = Wh; pa.Wl = Wl; pa.ldz = kcap;
+      pa.Zh = Zh; pa.Zl = Zl; pa.Wh = Wh; pa.Wl = Wl; pa.zblk = (long)KS * N;
       {
         const long tot = (long)pa.npairs * N * nc;
         ProfScope ps(h, "moments.pair", 0.0, 4.0 * 2.0 * tot + 8.0 * N * (double)Kc);
@@ -899,7 +908,7 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
       kper = (kper + KS - 1) / KS * KS;
       nsplit = (int)((Kc + kper - 1) / kper);
       SyrkArgs ya;
-      ya.Zh = Zh; ya.Zl = Zl; ya.Wh = Wh; ya.Wl = Wl; ya.ldz = kcap;
+      ya.Zh = Zh; ya.Zl = Zl; ya.Wh = Wh; ya.Wl = Wl; ya.zblk = (long)KS * N;
       ya.N = N; ya.K = Kc; ya.kper = kper;
       ya.u0scale = sc.u0scale; ya.u1scale = sc.u1scale;
       ya.part = part; ya.part_stride = part_stride;
