@@ -135,8 +135,8 @@ __global__ void row_stats_kernel(const double* in, long s_in_a, long s_in_b, int
 template <bool F16>
 __global__ void split_rows_kernel(const double* in, long s_in_a, long s_in_b, int nb,
                                   const int* perm, u16* hi, u16* lo, long s_out_a,
-                                  long s_out_b, int Qs, long rows, const int* gexp, long gsa,
-                                  long gsb) {
+                                  long s_out_b, long kblk, int Qs, long rows, const int* gexp,
+                                  long gsa, long gsb) {
   const long tot = rows * Qs;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < tot;
        idx += (long)gridDim.x * blockDim.x) {
@@ -148,7 +148,7 @@ __global__ void split_rows_kernel(const double* in, long s_in_a, long s_in_b, in
     if (gexp) x = ldexp(x, EMAX - gexp[ia * gsa + ib * gsb]);
     u16 h, l;
     split<F16>((float)x, h, l);
-    const long o = ia * s_out_a + ib * s_out_b + q;
+    const long o = (q / KS) * kblk + (ia * s_out_a + ib * s_out_b) * KS + (q % KS);
     hi[o] = h;
     lo[o] = l;
   }
@@ -159,9 +159,13 @@ __global__ void split_rows_kernel(const double* in, long s_in_a, long s_in_b, in
 // for p in a row block and q in a column block, with rows and columns
 // addressed through (pole, index) pairs. 256x320 output tiles, eight waves of
 // 128x80 (8x5 MFMA blocks each, two waves per SIMD), float32 accumulators.
+// The 16-bit operand arrays are K-blocked: element (row r, Q index k) sits at
+// (k / KS) kblk + r KS + k % KS, kblk = KS x (rows of the whole array), so the
+// KS columns of consecutive rows that one step reads are contiguous.
 struct XgemmArgs {
   const u16* Ah; const u16* Al; long sAp, sAx; int mA;   // row m: (m / mA) sAp + (m % mA) sAx
   const u16* Bh; const u16* Bl; long sBq, sBc; int nB;   // row n: (n / nB) sBq + (n % nB) sBc
+  long kblkA, kblkB;                                      // K-block strides (elements)
   int M, Nn, Qs;
   float* C; long ldc;
   int tiles_m, tiles_n;
@@ -220,12 +224,12 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
     const int kvg = (lane & 3) ^ swz(r);
     if (isa) {
       const int m = min(m0 + r, a.M - 1);
-      src[j] = (plane == 0 ? a.Ah : a.Al) + (long)(m / a.mA) * a.sAp +
-               (long)(m % a.mA) * a.sAx + 8 * kvg;
+      src[j] = (plane == 0 ? a.Ah : a.Al) +
+               ((long)(m / a.mA) * a.sAp + (long)(m % a.mA) * a.sAx) * KS + 8 * kvg;
     } else {
       const int n = min(n0 + r, a.Nn - 1);
-      src[j] = (plane == 0 ? a.Bh : a.Bl) + (long)(n / a.nB) * a.sBq +
-               (long)(n % a.nB) * a.sBc + 8 * kvg;
+      src[j] = (plane == 0 ? a.Bh : a.Bl) +
+               ((long)(n / a.nB) * a.sBq + (long)(n % a.nB) * a.sBc) * KS + 8 * kvg;
     }
   }
   typedef u16x8 StageA[2][GT][KV];
@@ -238,7 +242,8 @@ __global__ __launch_bounds__(XNT) void xgemm_split_kernel(XgemmBatch b) {
       const int b2 = isa ? bl : bl - 32;
       const int plane = isa ? b2 >> 4 : b2 / 20, row0 = 16 * (isa ? b2 & 15 : b2 % 20);
       u16x8* dst = isa ? &dA[plane][row0][0] : &dB[plane][row0][0];
-      __builtin_amdgcn_global_load_lds((const void*)(src[j] + kb),
+      const long kofs = (long)(kb / KS) * (isa ? a.kblkA : a.kblkB);
+      __builtin_amdgcn_global_load_lds((const void*)(src[j] + kofs),
                                        (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
     }
   };
@@ -653,16 +658,21 @@ __global__ __launch_bounds__(SNT) void syrk_split_kernel(SyrkArgs a) {
       }
 }
 
+// Rows (ia, ib) of `in` (float64, Q index permuted by perm) as 16-bit pairs
+// in the K-blocked layout: output row ia s_out_a + ib s_out_b (in rows) of an
+// array whose K blocks are kblk elements apart; hi and lo point at this
+// chunk's first row.
 template <bool F16>
 void split_rows(const double* in, long s_in_a, long s_in_b, int na, int nb, const int* perm,
-                u16* hi, u16* lo, long s_out_a, long s_out_b, int Qs, const int* gexp, long gsa,
-                long gsb, hipStream_t st) {
+                u16* hi, u16* lo, long s_out_a, long s_out_b, long kblk, int Qs,
+                const int* gexp, long gsa, long gsb, hipStream_t st) {
   const long rows = (long)na * nb;
   const long tot = rows * Qs;
   if (tot == 0) return;
   const long blocks = std::min<long>((tot + 255) / 256, 16384);
   hipLaunchKernelGGL((split_rows_kernel<F16>), dim3(blocks), dim3(256), 0, st, in, s_in_a,
-                     s_in_b, nb, perm, hi, lo, s_out_a, s_out_b, Qs, rows, gexp, gsa, gsb);
+                     s_in_b, nb, perm, hi, lo, s_out_a, s_out_b, kblk, Qs, rows, gexp, gsa,
+                     gsb);
   AGF2_CHECK_LAUNCH();
 }
 
@@ -752,8 +762,9 @@ int choose_splits(long Kc, int tiles, int nmax, int slots) {
 
 template <bool F16>
 static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, const u16* Rl,
-                               long sRp, long sRx, const u16* Sh, const u16* Sl, long sSp,
-                               long sSc, const double* ep, int np, const double* ec, int nc,
+                               long sRp, long sRx, long kblkR, const u16* Sh, const u16* Sl,
+                               long sSp, long sSc, long kblkS, const double* ep, int np,
+                               const double* ec, int nc,
                                const PartScales& sc, double* U0, double* U1) {
   hipStream_t st = h.stream;
   const long nn = (long)N * N;
@@ -819,8 +830,10 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
 
   auto problem = [&](int prow, int nrow, int pcol, int ncol, float* C) {
     XgemmArgs g;
-    g.Ah = Rh + (long)prow * sRp; g.Al = Rl + (long)prow * sRp; g.sAp = sRp; g.sAx = sRx; g.mA = N;
-    g.Bh = Sh + (long)pcol * sSp; g.Bl = Sl + (long)pcol * sSp; g.sBq = sSp; g.sBc = sSc;
+    g.Ah = Rh + (long)prow * sRp * KS; g.Al = Rl + (long)prow * sRp * KS;
+    g.sAp = sRp; g.sAx = sRx; g.mA = N; g.kblkA = kblkR;
+    g.Bh = Sh + (long)pcol * sSp * KS; g.Bl = Sl + (long)pcol * sSp * KS;
+    g.sBq = sSp; g.sBc = sSc; g.kblkB = kblkS;
     g.nB = nc;
     g.M = nrow * N; g.Nn = ncol * nc; g.Qs = Qs;
     g.C = C; g.ldc = (long)ncol * nc;
@@ -991,24 +1004,24 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
       pole_transform_f64(N, Q, Qp, L, u, npole, p0, np, T, st);
       // rows (p, x); one exponent per pole p
       if (F16) row_stats(T, per_pole, Qp, np, N, Q, 1, 0, eRo + p0, nrm + 0, st);
-      split_rows<F16>(T, per_pole, Qp, np, N, perm, Rxo_h + (long)p0 * N * Qs,
-                      Rxo_l + (long)p0 * N * Qs, (long)N * Qs, Qs, Qs,
+      split_rows<F16>(T, per_pole, Qp, np, N, perm, Rxo_h + (long)p0 * N * KS,
+                      Rxo_l + (long)p0 * N * KS, N, 1, (long)o * N * KS, Qs,
                       F16 ? eRo + p0 : nullptr, 1, 0, st);
     }
     for (int a0 = 0; a0 < v; a0 += pc) {
       const int na = std::min(pc, v - a0);
       pole_transform_f64(N, Q, Qp, L, u, npole, o + a0, na, T, st);
       if (F16) row_stats(T, per_pole, Qp, na, N, Q, 1, 0, eRv + a0, nrm + 1, st);
-      split_rows<F16>(T, per_pole, Qp, na, N, perm, Rxv_h + (long)a0 * N * Qs,
-                      Rxv_l + (long)a0 * N * Qs, (long)N * Qs, Qs, Qs,
+      split_rows<F16>(T, per_pole, Qp, na, N, perm, Rxv_h + (long)a0 * N * KS,
+                      Rxv_l + (long)a0 * N * KS, N, 1, (long)v * N * KS, Qs,
                       F16 ? eRv + a0 : nullptr, 1, 0, st);
       // Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q] for this chunk of a
       lov_transform_f64(N, Q, Qp, u, npole, o, na, T, Tov, st);
       // rows (i, a); one exponent per row, stored at i * v + a
       if (F16) row_stats(Tov, (long)na * Qp, Qp, o, na, Q, v, 1, eOV + a0, nrm + 2, st);
-      split_rows<F16>(Tov, (long)na * Qp, Qp, o, na, perm, Rov_h + (long)a0 * Qs,
-                      Rov_l + (long)a0 * Qs, (long)v * Qs, Qs, Qs, F16 ? eOV + a0 : nullptr,
-                      v, 1, st);
+      split_rows<F16>(Tov, (long)na * Qp, Qp, o, na, perm, Rov_h + (long)a0 * KS,
+                      Rov_l + (long)a0 * KS, v, 1, (long)o * v * KS, Qs,
+                      F16 ? eOV + a0 : nullptr, v, 1, st);
     }
   }
   PartScales lesser, greater;
@@ -1045,10 +1058,11 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
     lesser = make(eRo, eOV, n2[0], 2.0 * eo_max + ev_max, (long)v, 1L);
     greater = make(eRv, eVO, n2[1], 2.0 * ev_max + eo_max, (long)o, 1L);
   }
-  moments_part_split<F16>(h, N, Q, Qs, Rxo_h, Rxo_l, (long)N * Qs, Qs, Rov_h, Rov_l,
-                          (long)v * Qs, Qs, e, o, e + o, v, lesser, m0o, m1o);
-  moments_part_split<F16>(h, N, Q, Qs, Rxv_h, Rxv_l, (long)N * Qs, Qs, Rov_h, Rov_l, Qs,
-                          (long)v * Qs, e + o, v, e, o, greater, m0v, m1v);
+  // strides in rows of the K-blocked arrays
+  moments_part_split<F16>(h, N, Q, Qs, Rxo_h, Rxo_l, N, 1, (long)o * N * KS, Rov_h, Rov_l, v,
+                          1, (long)o * v * KS, e, o, e + o, v, lesser, m0o, m1o);
+  moments_part_split<F16>(h, N, Q, Qs, Rxv_h, Rxv_l, N, 1, (long)v * N * KS, Rov_h, Rov_l, 1,
+                          v, (long)o * v * KS, e + o, v, e, o, greater, m0v, m1v);
 }
 
 void build_moments_split(Handle& h, int N, int Q, const double* L, int npole, int nocc,
