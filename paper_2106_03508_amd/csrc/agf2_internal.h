@@ -222,7 +222,7 @@ struct Handle {
   rocblas_handle blas = nullptr;
   std::string last_error;
   // workspace pools
-  DevBuf ws_moments[8];
+  DevBuf ws_moments[9];
   DevBuf ws_fock[8];
   DevBuf ws_misc[8];
   DevBuf ws_run[8];

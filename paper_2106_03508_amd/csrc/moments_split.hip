@@ -953,6 +953,10 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
   u16 *Rxo_h = Sxo, *Rxo_l = Sxo + (long)o * N * Qs;
   u16 *Rxv_h = Sxv, *Rxv_l = Sxv + (long)v * N * Qs;
   u16 *Rov_h = Sov, *Rov_l = Sov + (long)o * v * Qs;
+  // the same tensor with rows (a, i): the greater part's inner pole i is then
+  // the contiguous row index of its B operand
+  u16* Svo = h.ws_moments[8].as<u16>(2L * o * v * Qs);
+  u16 *Rvo_h = Svo, *Rvo_l = Svo + (long)o * v * Qs;
   // fp16 scale exponents: per occupied pole, per virtual pole, per (i, a) row;
   // then the squared-norm maxima of the three tensors' Q rows
   int* ex = h.ws_misc[7].as<int>((long)npole + 2L * o * v + 8);
@@ -1022,6 +1026,9 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
       split_rows<F16>(Tov, (long)na * Qp, Qp, o, na, perm, Rov_h + (long)a0 * KS,
                       Rov_l + (long)a0 * KS, v, 1, (long)o * v * KS, Qs,
                       F16 ? eOV + a0 : nullptr, v, 1, st);
+      split_rows<F16>(Tov, (long)na * Qp, Qp, o, na, perm, Rvo_h + (long)a0 * o * KS,
+                      Rvo_l + (long)a0 * o * KS, 1, o, (long)o * v * KS, Qs,
+                      F16 ? eOV + a0 : nullptr, v, 1, st);
     }
   }
   PartScales lesser, greater;
@@ -1061,8 +1068,8 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
   // strides in rows of the K-blocked arrays
   moments_part_split<F16>(h, N, Q, Qs, Rxo_h, Rxo_l, N, 1, (long)o * N * KS, Rov_h, Rov_l, v,
                           1, (long)o * v * KS, e, o, e + o, v, lesser, m0o, m1o);
-  moments_part_split<F16>(h, N, Q, Qs, Rxv_h, Rxv_l, N, 1, (long)v * N * KS, Rov_h, Rov_l, 1,
-                          v, (long)o * v * KS, e + o, v, e, o, greater, m0v, m1v);
+  moments_part_split<F16>(h, N, Q, Qs, Rxv_h, Rxv_l, N, 1, (long)v * N * KS, Rvo_h, Rvo_l, o,
+                          1, (long)o * v * KS, e + o, v, e, o, greater, m0v, m1v);
 }
 
 void build_moments_split(Handle& h, int N, int Q, const double* L, int npole, int nocc,
