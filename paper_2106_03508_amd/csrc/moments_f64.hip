@@ -166,6 +166,152 @@ __global__ __launch_bounds__(NT) void slab_f64_kernel(SlabF64 a) {
   slab_tile<TC>(a, xcd_remap(blockIdx.x, G), A1, A2, B1, B2);
 }
 
+// Wide slab tile for one-job launches: 128 x rows by TC inner columns, eight
+// waves arranged WX x (8 / WX), each owning (128 / WX) rows x (TC / (8 / WX))
+// columns of both mirrored products, one workgroup per CU (double-buffered
+// LDS, 107 KiB at TC = 80). Per K step it moves 2 (128 + TC) operand rows for
+// 4 x 128 x TC x 16 flops: 12.3 flops per byte at TC = 80 against 5.3 for the
+// 64 x 32 tile, and up to 0.83 MFMAs per LDS read against 0.67. Same epilogue
+// as slab_tile.
+constexpr int TBW = 128, LDW = TBW + 1, NTW = 512;
+template <int TC, int WX>
+__global__ __launch_bounds__(NTW) void slab_f64_wide(SlabF64 a) {
+  constexpr int WC = 8 / WX;
+  constexpr int RB = TBW / WX / 16;   // row blocks per wave
+  constexpr int CBW = TC / WC / 16;   // column blocks per wave
+  constexpr int LDC = TC + 1;
+  constexpr int NA = TBW / 32;        // A rows per thread and array (32 rows per pass)
+  constexpr int NBR = (TC + 31) / 32; // B passes (the last may be partial)
+  static_assert(RB * WX * 16 == TBW && CBW * WC * 16 == TC, "wave tiling");
+  __shared__ double A1[2][BK][LDW], A2[2][BK][LDW], B1[2][BK][LDC], B2[2][BK][LDC];
+  const long G = (long)a.npairs * a.tiles_x * a.tiles_c;
+  const long logical = xcd_remap(blockIdx.x, G);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per_pair = a.tiles_x * a.tiles_c;
+  const int P = a.pair0 + (int)(logical / per_pair);
+  const int rem = (int)(logical % per_pair);
+  const int xt = rem % a.tiles_x, ct = rem / a.tiles_x;
+  const int p = a.pi[P], q = a.pj[P];
+  const bool diag = (p == q);
+  const int x0 = xt * TBW, c0 = ct * TC;
+  const double* Rp = a.R + (long)p * a.sRp;
+  const double* Rq = a.R + (long)q * a.sRp;
+  const double* Sq = a.S + (long)q * a.sSp;
+  const double* Sp = a.S + (long)p * a.sSp;
+
+  // loader: thread -> k = tid % 16, rows tid / 16 + 32 i. Rows past N and
+  // columns past nc read the last row / column (their outputs are not
+  // stored); B rows past TC in the last pass (a whole wave's rows) are skipped.
+  const int lk = tid & 15, lr = tid >> 4;
+  long orow[NA], ocol[NBR];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) orow[i] = (long)min(x0 + lr + 32 * i, a.N - 1) * a.sRx + lk;
+#pragma unroll
+  for (int i = 0; i < NBR; ++i) ocol[i] = (long)min(c0 + lr + 32 * i, a.nc - 1) * a.sSc + lk;
+  double r1[NA], r2[NA], s1[NBR], s2[NBR];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      r1[i] = Rp[orow[i] + kb];
+      r2[i] = Rq[orow[i] + kb];
+    }
+#pragma unroll
+    for (int i = 0; i < NBR; ++i) {
+      if (lr + 32 * i < TC) {
+        s1[i] = Sq[ocol[i] + kb];
+        s2[i] = Sp[ocol[i] + kb];
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      A1[buf][lk][lr + 32 * i] = r1[i];
+      A2[buf][lk][lr + 32 * i] = r2[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NBR; ++i) {
+      if (lr + 32 * i < TC) {
+        B1[buf][lk][lr + 32 * i] = s1[i];
+        B2[buf][lk][lr + 32 * i] = s2[i];
+      }
+    }
+  };
+
+  const int fr = lane & 15, fk = lane >> 4;
+  const int wr = (wave % WX) * (TBW / WX), wcol = (wave / WX) * (TC / WC);
+  d4 c1[RB][CBW], c2[RB][CBW];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CBW; ++j) {
+      c1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      c2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int nsteps = a.Qp / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  // The mirrored product runs for diagonal pairs too (its result is unused),
+  // so the MFMA loop has no branch.
+  for (int step = 0; step < nsteps; ++step) {
+    const int buf = step & 1;
+    load(min(step + 1, nsteps - 1) * BK);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double xa1[RB], xa2[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        xa1[i] = A1[buf][kk + fk][wr + 16 * i + fr];
+        xa2[i] = A2[buf][kk + fk][wr + 16 * i + fr];
+      }
+#pragma unroll
+      for (int j = 0; j < CBW; ++j) {
+        const double b1 = B1[buf][kk + fk][wcol + 16 * j + fr];
+        const double b2 = B2[buf][kk + fk][wcol + 16 * j + fr];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          c1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa1[i], b1, c1[i][j], 0, 0, 0);
+          c2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa2[i], b2, c2[i][j], 0, 0, 0);
+        }
+      }
+    }
+    store(buf ^ 1);
+    __syncthreads();
+  }
+
+  const long col0 = a.pcol[P] - a.col_base;
+  const double cp = 0.70710678118654752440;   // sqrt(1/2)
+  const double cm = 1.22474487139158904910;   // sqrt(3/2)
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CBW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + wr + 16 * i + fk + 4 * r;
+        const int c = c0 + wcol + 16 * j + fr;
+        if (x >= a.N || c >= a.nc) continue;
+        double* z = a.Z + (long)x * a.ldz + col0 + c;
+        if (diag) {
+          z[0] = c1[i][j][r];
+        } else {
+          const double u = c1[i][j][r], v = c2[i][j][r];
+          z[0] = cp * (u + v);
+          z[a.nc] = cm * (u - v);
+        }
+      }
+  if (xt == 0 && tid < TC) {
+    const int c = c0 + tid;
+    if (c < a.nc) {
+      const double wgt = a.ep[p] + a.ep[q] - a.ec[c];
+      a.w[col0 + c] = wgt;
+      if (!diag) a.w[col0 + a.nc + c] = wgt;
+    }
+  }
+}
+
 // Job owning global work index `it`: the largest j with prefix[j] <= it
 // (jobs with no work share their prefix with the next job and are skipped).
 __device__ __forceinline__ int find_job(const long* prefix, int njobs, long it) {
@@ -380,6 +526,34 @@ void launch_slab_f64(int tc, const SlabF64& a, hipStream_t st) {
   AGF2_CHECK_LAUNCH();
 }
 
+// One-job launches use the 128-row tile when the x range pads to at most 15%
+// more rows than with 64-row tiles; its inner width is the cheapest of 80, 64
+// and 32 in padded columns plus a fixed 16 per tile.
+bool slab_f64_use_wide(int N) {
+  return (long)((N + TBW - 1) / TBW) * TBW * 100 <= (long)((N + TB - 1) / TB) * TB * 115;
+}
+
+int slab_f64_wide_tc(int nc) {
+  int best = 80;
+  long best_cost = -1;
+  for (int tc : {80, 64, 32}) {
+    const long cost = (long)((nc + tc - 1) / tc) * (tc + 16);
+    if (best_cost < 0 || cost < best_cost) {
+      best = tc;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+void launch_slab_f64_wide(int tc, const SlabF64& a, hipStream_t st) {
+  const dim3 grid((unsigned)slab_f64_tiles(a));
+  if (tc == 80) hipLaunchKernelGGL((slab_f64_wide<80, 8>), grid, dim3(NTW), 0, st, a);
+  else if (tc == 64) hipLaunchKernelGGL((slab_f64_wide<64, 4>), grid, dim3(NTW), 0, st, a);
+  else hipLaunchKernelGGL((slab_f64_wide<32, 8>), grid, dim3(NTW), 0, st, a);
+  AGF2_CHECK_LAUNCH();
+}
+
 void launch_syrk_f64(const SyrkF64& a, hipStream_t st) {
   hipLaunchKernelGGL(syrk_f64_kernel, dim3((unsigned)((long)a.tiles * a.nsplit)), dim3(NT), 0,
                      st, a);
@@ -515,7 +689,8 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
   double* part = h.ws_moments[5].as<double>(pair_stride * npm);
   fill_zero(part, pair_stride * npm, st);
 
-  const int tc = slab_f64_tc(nc);
+  const bool wide = slab_f64_use_wide(N);
+  const int tc = wide ? slab_f64_wide_tc(nc) : slab_f64_tc(nc);
   int P0 = 0;
   while (P0 < npairs) {
     int P1 = P0;
@@ -530,13 +705,14 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
     sa.pi = d_pi; sa.pj = d_pj; sa.pcol = d_col;
     sa.pair0 = P0; sa.npairs = P1 - P0; sa.col_base = t.col[P0];
     sa.Z = Z; sa.ldz = kcap; sa.w = w;
-    sa.tiles_x = tiles_n; sa.tiles_c = (nc + tc - 1) / tc;
+    sa.tiles_x = wide ? (N + TBW - 1) / TBW : tiles_n; sa.tiles_c = (nc + tc - 1) / tc;
     {
       // algorithmic: 2 N nc Q per (p,q) slab, two slabs per off-diagonal pair;
       // bytes: the Z chunk and its weights written once
       const double slabs = (double)(2 * (P1 - P0)) - (double)ndiag(t, P0, P1);
       ProfScope ps(h, "moments.slab", slabs * 2.0 * N * nc * Q, 8.0 * (N + 1.0) * Kc);
-      launch_slab_f64(tc, sa, st);
+      if (wide) launch_slab_f64_wide(tc, sa, st);
+      else launch_slab_f64(tc, sa, st);
     }
 
     int nsplit = (int)std::min<long>(nsplit_max, std::max<long>(1, Kc / 256));
