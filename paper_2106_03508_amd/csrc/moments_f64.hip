@@ -461,6 +461,118 @@ __global__ __launch_bounds__(NT) void syrk_f64_kernel(SyrkF64 a) {
   syrk_tile<false>(a, (int)(item % a.tiles), (int)(item / a.tiles), X, Y, W);
 }
 
+// Wide SYRK tile for one-job launches: lower-triangle 128 x 128 tiles (tile
+// t of the 128-row triangle), eight waves of 32 x rows by 64 y rows with both
+// moments, one workgroup per CU. A K step moves 256 operand rows for
+// 2 x 2 x 128 x 128 x 16 flops (32 flops per byte, against 16 for the 64-row
+// tile) and 2.3 MFMAs per LDS read. Waves whose sub-tile lies wholly above
+// the diagonal skip their MFMAs and stores; only the lower triangle of the
+// partial slots is read by the reduction. Loads carry no condition (rows past
+// N read row N - 1, columns past the split's end read its last column and
+// are replaced by zero).
+constexpr int NTS = 512;
+__global__ __launch_bounds__(NTS) void syrk_f64_wide(SyrkF64 a) {
+  __shared__ double X[2][BK][LDW], Y[2][BK][LDW], W[2][BK];
+  const long item = xcd_remap(blockIdx.x, (long)a.tiles * a.nsplit);
+  const int t = (int)(item % a.tiles), s = (int)(item / a.tiles);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int xt = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((xt + 1) * (xt + 2) / 2 <= t) ++xt;
+  while (xt * (xt + 1) / 2 > t) --xt;
+  const int yt = t - xt * (xt + 1) / 2;
+  const long k0 = (long)s * a.kper, k1 = std::min(a.K, k0 + a.kper);
+  if (k1 <= k0) return;   // uniform over the workgroup
+  const int x0 = xt * TBW, y0 = yt * TBW;
+  const int lk = tid & 15, lr = tid >> 4;   // 32 rows per pass, 4 passes
+  long ox[4], oy[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ox[i] = (long)min(x0 + lr + 32 * i, a.N - 1) * a.ldz;
+    oy[i] = (long)min(y0 + lr + 32 * i, a.N - 1) * a.ldz;
+  }
+  double rx[4], ry[4], rw = 0.0;
+  auto load = [&](long kb) {
+    const long k = kb + lk;
+    const bool kin = k < k1;
+    const long kc = kin ? k : k1 - 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double vx = a.Z[ox[i] + kc], vy = a.Z[oy[i] + kc];
+      rx[i] = kin ? vx : 0.0;
+      ry[i] = kin ? vy : 0.0;
+    }
+    const double vw = a.w[kc];
+    rw = kin ? vw : 0.0;
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      X[buf][lk][lr + 32 * i] = rx[i];
+      Y[buf][lk][lr + 32 * i] = ry[i];
+    }
+    if (tid < BK) W[buf][tid] = rw;
+  };
+  const int wm = (wave & 3) * 32, wn = (wave >> 2) * 64;
+  const bool active = x0 + wm + 31 >= y0 + wn;   // some element on or below the diagonal
+  const int fr = lane & 15, fk = lane >> 4;
+  d4 u0[2][4], u1[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      u0[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      u1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const long nsteps = (k1 - k0 + BK - 1) / BK;
+  load(k0);
+  store(0);
+  __syncthreads();
+  for (long step = 0; step < nsteps; ++step) {
+    const int buf = step & 1;
+    load(k0 + min(step + 1, nsteps - 1) * BK);
+    __builtin_amdgcn_sched_barrier(0);
+    if (active) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const double wk = W[buf][kk + fk];
+        double xa[2], xw[2], yb[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          xa[i] = X[buf][kk + fk][wm + 16 * i + fr];
+          xw[i] = xa[i] * wk;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) yb[j] = Y[buf][kk + fk][wn + 16 * j + fr];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            u0[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], yb[j], u0[i][j], 0, 0, 0);
+            u1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xw[i], yb[j], u1[i][j], 0, 0, 0);
+          }
+      }
+    }
+    store(buf ^ 1);   // the last step writes the idle buffer
+    __syncthreads();
+  }
+  if (!active) return;
+  double* P0 = a.part + (long)s * a.part_stride;
+  double* P1 = P0 + (long)a.N * a.N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + wm + 16 * i + fk + 4 * r;
+        const int y = y0 + wn + 16 * j + fr;
+        if (x >= a.N || y > x) continue;
+        const long o = (long)x * a.N + y;
+        P0[o] += u0[i][j][r];
+        P1[o] += u1[i][j][r];
+      }
+}
+
 __global__ __launch_bounds__(NT) void syrk_f64_grouped(const SyrkF64* jobs, const long* prefix,
                                                        int njobs, long total) {
   __shared__ double X[2][BK][LD], Y[2][BK][LD], W[2][BK];
@@ -551,6 +663,12 @@ void launch_slab_f64_wide(int tc, const SlabF64& a, hipStream_t st) {
   if (tc == 80) hipLaunchKernelGGL((slab_f64_wide<80, 8>), grid, dim3(NTW), 0, st, a);
   else if (tc == 64) hipLaunchKernelGGL((slab_f64_wide<64, 4>), grid, dim3(NTW), 0, st, a);
   else hipLaunchKernelGGL((slab_f64_wide<32, 8>), grid, dim3(NTW), 0, st, a);
+  AGF2_CHECK_LAUNCH();
+}
+
+void launch_syrk_f64_wide(const SyrkF64& a, hipStream_t st) {
+  hipLaunchKernelGGL(syrk_f64_wide, dim3((unsigned)((long)a.tiles * a.nsplit)), dim3(NTS), 0,
+                     st, a);
   AGF2_CHECK_LAUNCH();
 }
 
@@ -682,14 +800,15 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
   double* w = Z + (long)N * kcap;
 
   const int tiles_n = (N + TB - 1) / TB;
-  const int nlower = tiles_n * (tiles_n + 1) / 2;
+  const bool wide = slab_f64_use_wide(N);   // 128-row slab and SYRK tiles
+  const int tiles_w = (N + TBW - 1) / TBW;
+  const int nlower = wide ? tiles_w * (tiles_w + 1) / 2 : tiles_n * (tiles_n + 1) / 2;
   const int nsplit_max = std::max(1, std::min(64, (2048 + nlower - 1) / nlower));
   const long part_stride = 2 * nn;
   const long pair_stride = part_stride * nsplit_max;
   double* part = h.ws_moments[5].as<double>(pair_stride * npm);
   fill_zero(part, pair_stride * npm, st);
 
-  const bool wide = slab_f64_use_wide(N);
   const int tc = wide ? slab_f64_wide_tc(nc) : slab_f64_tc(nc);
   int P0 = 0;
   while (P0 < npairs) {
@@ -731,7 +850,8 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
       ya.part = part + m * pair_stride;
       // algorithmic: lower triangles of two symmetric N x N products over Kc
       ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 1.0) * Kc);
-      launch_syrk_f64(ya, st);
+      if (wide) launch_syrk_f64_wide(ya, st);
+      else launch_syrk_f64(ya, st);
     }
     P0 = P1;
   }
