@@ -447,6 +447,104 @@ __global__ __launch_bounds__(256) void pair_split_kernel(PairArgs a) {
   }
 }
 
+// Pairing where every pair's P and M column blocks are ncp columns long, ncp a
+// multiple of KS (the last ncp - nc columns of each block are zero), so that
+// each K block of Z lies in one block of one pair. A workgroup takes one pair
+// and 16 rows x; thread t owns row x0 + t / 16 and the columns 2 (t % 16) and
+// 2 (t % 16) + 1 of every K block of the pair, walking the K blocks UK at a
+// time. A wave then stores four consecutive rows of one K block, 256
+// contiguous bytes per plane, and reads 128 contiguous bytes of each of its
+// four slab rows. V2: nc even, so the slab reads are 8-byte aligned float2.
+template <bool F16, bool V2>
+__global__ __launch_bounds__(256) void pair_split_blk_kernel(PairArgs a, int ncp) {
+  constexpr int UK = 4;
+  const long logical = xcd_remap(blockIdx.x, (long)gridDim.x);
+  const int xg = (int)(logical / a.npairs), pr = (int)(logical % a.npairs);
+  const int p = a.pa[pr], q = a.pb[pr];
+  const bool diag = (p == q);
+  const long kb0 = (a.pcol[pr] - a.col_base) / KS;   // first K block of the P columns
+  const int nkb = ncp / KS;
+  const float* r1 = a.X1 + (long)(p - a.P0) * a.N * a.ld1 + (long)(q - a.P1) * a.nc;
+  const float* r2 = (a.P0 == a.P1)
+                        ? a.X1 + (long)(q - a.P0) * a.N * a.ld1 + (long)(p - a.P1) * a.nc
+                        : a.X2 + (long)(q - a.P1) * a.N * a.ld2 + (long)(p - a.P0) * a.nc;
+  const long ld2 = (a.P0 == a.P1) ? a.ld1 : a.ld2;
+  extern __shared__ int ptab[];
+  int* t1 = ptab;
+  int* t2 = ptab + a.nc;
+  float* tw = reinterpret_cast<float*>(ptab + 2 * a.nc);
+  for (int cc = threadIdx.x; cc < a.nc; cc += 256) {
+    if constexpr (F16) {
+      t1[cc] = a.eR[p] + a.eS[(long)q * a.sEp + (long)cc * a.sEc] - 2 * EMAX;
+      t2[cc] = diag ? 0 : a.eR[q] + a.eS[(long)p * a.sEp + (long)cc * a.sEc] - 2 * EMAX;
+    }
+    tw[cc] = (float)(a.ep[p] + a.ep[q] - a.ec[cc]);
+  }
+  __syncthreads();
+  const int x = xg * 16 + (int)(threadIdx.x / 16);
+  if (x >= a.N) return;   // no barrier follows
+  const int cl = 2 * (int)(threadIdx.x % 16);
+  const float* row1 = r1 + (long)x * a.ld1;
+  const float* row2 = r2 + (long)x * ld2;
+  const long zrow = (long)x * KS + cl;
+  u16* dst[4] = {a.Zh, a.Zl, a.Wh, a.Wl};
+  for (int kb = 0; kb < nkb; kb += UK) {
+    float x1[UK][2], x2[UK][2];
+#pragma unroll
+    for (int u = 0; u < UK; ++u) {
+      const int c = (kb + u) * KS + cl;
+      x1[u][0] = x1[u][1] = x2[u][0] = x2[u][1] = 0.f;
+      if constexpr (V2) {
+        if (c < a.nc) {   // nc even: c + 1 < nc too
+          const float2 v1 = *reinterpret_cast<const float2*>(row1 + c);
+          x1[u][0] = v1.x; x1[u][1] = v1.y;
+          if (!diag) {
+            const float2 v2 = *reinterpret_cast<const float2*>(row2 + c);
+            x2[u][0] = v2.x; x2[u][1] = v2.y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+          if (c + t < a.nc) {
+            x1[u][t] = row1[c + t];
+            if (!diag) x2[u][t] = row2[c + t];
+          }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UK; ++u) {
+      if (kb + u >= nkb) break;
+      const int c = (kb + u) * KS + cl;
+      u16 v[2][8];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int cc = c + t;
+        if (cc < a.nc) {
+          float y1 = x1[u][t], y2 = x2[u][t];
+          if constexpr (F16) {
+            y1 = ldexpf(y1, t1[cc]);
+            if (!diag) y2 = ldexpf(y2, t2[cc]);
+          }
+          pair_values<F16>(y1, y2, diag, tw[cc], a.zscale, a.wscale, v[t]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[t][k] = 0;   // padding column
+        }
+      }
+      const long o = (kb0 + kb + u) * a.zblk + zrow;          // P column block
+      const long om = (kb0 + nkb + kb + u) * a.zblk + zrow;   // M column block
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        *reinterpret_cast<unsigned*>(dst[k] + o) = (unsigned)v[0][k] | ((unsigned)v[1][k] << 16);
+        if (!diag)
+          *reinterpret_cast<unsigned*>(dst[k] + om) =
+              (unsigned)v[0][4 + k] | ((unsigned)v[1][4 + k] << 16);
+      }
+    }
+  }
+}
+
 // out[a][i] = in[i][a] (o x v ints)
 __global__ void transpose_int_kernel(int o, int v, const int* in, int* out) {
   const long n = (long)o * v;
@@ -780,21 +878,31 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
   int kb = (int)std::floor(std::sqrt((double)(1L << 26) / ((double)N * nc)));
   kb = std::max(1, std::min({kb, np, 255}));   // <= 255^2 pairs per chunk (grid y limit)
   const int nblk = (np + kb - 1) / kb;
+  // Each pair's P and M column blocks are padded with zero columns to a
+  // multiple of KS when that adds at most 1/32 of the columns: a K block of Z
+  // then lies in one block of one pair, and the pairing kernel stores whole
+  // K-block rows (pair_split_blk_kernel) instead of pieces shared by
+  // neighbouring pairs. The zero columns add nothing to the sums.
+  const int ncp_full = (nc + KS - 1) / KS * KS;
+  const bool padded = 32L * (ncp_full - nc) <= nc;
+  const int ncp = padded ? ncp_full : nc;
   // pair list ordered by block pair, with chunk-local column offsets
   std::vector<int> hpa, hpb;
   std::vector<long> hcol;
-  std::vector<long> chunk_first, chunk_cols;
+  std::vector<long> chunk_first, chunk_cols, chunk_cols_alg;
   for (int ib = 0; ib < nblk; ++ib)
     for (int jb = ib; jb < nblk; ++jb) {
       chunk_first.push_back((long)hpa.size());
-      long c0 = 0;
+      long c0 = 0, calg = 0;
       for (int p = ib * kb; p < std::min(np, (ib + 1) * kb); ++p)
         for (int q = jb * kb; q < std::min(np, (jb + 1) * kb); ++q) {
           if (ib == jb && q < p) continue;
           hpa.push_back(p); hpb.push_back(q); hcol.push_back(c0);
-          c0 += (p == q) ? nc : 2L * nc;
+          c0 += (p == q) ? ncp : 2L * ncp;
+          calg += (p == q) ? nc : 2L * nc;
         }
       chunk_cols.push_back(c0);
+      chunk_cols_alg.push_back(calg);
     }
   const long npairs = (long)hpa.size();
   int* d_pa = h.ws_moments[6].as<int>(2 * npairs);
@@ -895,7 +1003,21 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
       pa.zscale = sc.zscale; pa.wscale = sc.wscale;
       pa.ep = ep; pa.ec = ec;
       pa.Zh = Zh; pa.Zl = Zl; pa.Wh = Wh; pa.Wl = Wl; pa.zblk = (long)KS * N;
-      {
+      if (padded) {
+        const long tot = (long)pa.npairs * N * nc;
+        ProfScope ps(h, "moments.pair", 0.0, 4.0 * 2.0 * tot + 8.0 * N * (double)Kc);
+        const long nxg = (N + 15) / 16;
+        AGF2_REQUIRE(nxg * pa.npairs < (1L << 31), "pair chunk too large");
+        const dim3 grid((unsigned)(nxg * pa.npairs));
+        const size_t tab = 3 * sizeof(int) * (size_t)nc;
+        AGF2_REQUIRE(tab <= 64 * 1024, "pair chunk: inner pole count too large");
+        if (nc % 2 == 0)
+          hipLaunchKernelGGL((pair_split_blk_kernel<F16, true>), grid, dim3(256), tab, st, pa, ncp);
+        else
+          hipLaunchKernelGGL((pair_split_blk_kernel<F16, false>), grid, dim3(256), tab, st, pa,
+                             ncp);
+        AGF2_CHECK_LAUNCH();
+      } else {
         const long tot = (long)pa.npairs * N * nc;
         ProfScope ps(h, "moments.pair", 0.0, 4.0 * 2.0 * tot + 8.0 * N * (double)Kc);
         const bool two = (nc % 2 == 0) && (kcap % 2 == 0);
@@ -926,7 +1048,8 @@ static void moments_part_split(Handle& h, int N, int Q, int Qs, const u16* Rh, c
       ya.u0scale = sc.u0scale; ya.u1scale = sc.u1scale;
       ya.part = part; ya.part_stride = part_stride;
       {
-        ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Kc, 8.0 * (N + 0.0) * Kc);
+        const double Ka = (double)chunk_cols_alg[chunk];   // without padding columns
+        ProfScope ps(h, "moments.syrk", 2.0 * N * (N + 1.0) * Ka, 8.0 * (N + 0.0) * Ka);
         ya.tiles = ntiles; ya.nsplit = nsplit; ya.nxt = nxt;
         ya.lolo_all = lolo_all();
         hipLaunchKernelGGL((syrk_split_kernel<F16>), dim3((unsigned)(ntiles * nsplit)),

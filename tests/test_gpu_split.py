@@ -50,6 +50,9 @@ CASES = [
     ("dressed_tiles", 130, 100, ("dressed", 150, 40)),
     ("single_occ", 20, 33, ("hf", 1)),
     ("medium_hf", 200, 700, ("hf", 40)),
+    # lesser inner pole count 63: its pair column blocks are padded to 64
+    # (odd count, one zero column each); greater 57 is not padded
+    ("padded_pairs", 40, 70, ("dressed", 120, 57)),
 ]
 
 
