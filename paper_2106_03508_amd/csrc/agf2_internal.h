@@ -114,6 +114,9 @@ int grouped_grid_f64(int kind, int tc);
 void fill_zero(double* p, long n, hipStream_t st);
 void reduce_moment_partials(const double* part, long part_stride, int nsplit, int N,
                             double* U0, double* U1, hipStream_t st);
+// True when u (N x npole) is exactly the identity: the pole-basis transforms
+// may then take u = nullptr (a relayout of L instead of a product).
+bool poles_are_identity(Handle& h, int N, int npole, const double* u);
 void pole_transform_f64(int N, int Q, int Qp, const double* L, const double* u, int npole,
                         int p0, int np, double* T, hipStream_t st);
 void lov_transform_f64(int N, int Q, int Qp, const double* u, int npole, int o, int v,

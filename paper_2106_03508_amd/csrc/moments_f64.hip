@@ -23,6 +23,7 @@
 // fixed order, so results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "agf2_internal.h"
 
@@ -861,11 +862,97 @@ static void moments_part_f64(Handle& h, int N, int Q, int Qp, const double* R, l
                            U[2 * m + 1], st);
 }
 
+namespace {
+
+// flag = 1 unless u (n x n) is exactly the identity
+__global__ void identity_check_kernel(const double* u, int n, int* flag) {
+  const long nn = (long)n * n;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < nn;
+       k += (long)gridDim.x * blockDim.x) {
+    const long r = k / n, c = k - r * n;
+    if (u[k] != (r == c ? 1.0 : 0.0)) *flag = 1;
+  }
+}
+
+// T[p][x][q] = L[q][x][p0 + p] (zero for q >= Q) through 32 x 32 LDS tiles of
+// (q, p) per row x: 256-byte runs of p read, 256-byte runs of q written.
+// Adding +0.0 turns a -0.0 into the +0.0 that the product with the identity
+// gives, so the copy equals that product bit for bit.
+__global__ __launch_bounds__(256) void transpose_poles_kernel(const double* L, int N, int Q,
+                                                              int Qp, int p0, int np,
+                                                              int qtiles, double* T) {
+  __shared__ double tile[32][33];
+  const int x = (int)(blockIdx.x / qtiles);
+  const int q0 = (int)(blockIdx.x % qtiles) * 32;
+  const int pb = (int)blockIdx.y * 32;
+  const int tx = (int)(threadIdx.x % 32), ty = (int)(threadIdx.x / 32);
+  const long nn = (long)N * N;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int q = q0 + ty + 8 * r, p = pb + tx;
+    tile[ty + 8 * r][tx] =
+        (q < Q && p < np) ? L[(long)q * nn + (long)x * N + p0 + p] + 0.0 : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int p = pb + ty + 8 * r, q = q0 + tx;
+    if (p < np && q < Qp) T[((long)p * N + x) * Qp + q] = tile[tx][ty + 8 * r];
+  }
+}
+
+// out[i][a][q] = in[a][i][q] for i < o, a < na, q < Qp
+__global__ void select_rows_kernel(const double* in, int N, int o, int na, int Qp,
+                                   double* out) {
+  const long tot = (long)o * na * Qp;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < tot;
+       k += (long)gridDim.x * blockDim.x) {
+    const long r = k / Qp;
+    const int q = (int)(k - r * Qp);
+    const int a = (int)(r % na), i = (int)(r / na);
+    out[k] = in[((long)a * N + i) * Qp + q];
+  }
+}
+
+}  // namespace
+
+// Mean-field poles (the first iteration from the mean-field reference: one
+// pole per orbital with unit coefficients) make the pole-basis transform a
+// relayout of L. True when npole = N and u is exactly the identity (checked
+// on the device; one host synchronisation). AGF2_NO_IDENTITY_TRANSFORM=1 in
+// the environment turns the check off, so every transform runs as a product
+// with u (a check that both give the same bits).
+bool poles_are_identity(Handle& h, int N, int npole, const double* u) {
+  if (npole != N || N == 0) return false;
+  const char* env = std::getenv("AGF2_NO_IDENTITY_TRANSFORM");
+  if (env && env[0] == '1') return false;
+  int* flag = reinterpret_cast<int*>(h.ws_red.as<double>(4096) + 4004);
+  AGF2_HIP(hipMemsetAsync(flag, 0, sizeof(int), h.stream));
+  const long nn = (long)N * N;
+  const unsigned blocks = (unsigned)std::min<long>((nn + 255) / 256, 4096);
+  hipLaunchKernelGGL(identity_check_kernel, dim3(blocks), dim3(256), 0, h.stream, u, N, flag);
+  AGF2_CHECK_LAUNCH();
+  int hf = 1;
+  AGF2_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+  AGF2_HIP(hipStreamSynchronize(h.stream));
+  return hf == 0;
+}
+
 // Pole-basis DF tensors, Q padded to Qp (a multiple of 16) with zeros:
 //   T[p][x][Q] = sum_r u[r][p0+p] L[Q][x][r]          (p in [0, np))
+// u = nullptr: identity coefficients, T[p][x][Q] = L[Q][x][p0+p].
 void pole_transform_f64(int N, int Q, int Qp, const double* L, const double* u, int npole,
                         int p0, int np, double* T, hipStream_t st) {
   if (np == 0) return;
+  if (!u) {
+    const long qtiles = (Qp + 31) / 32, ptiles = (np + 31) / 32;
+    AGF2_REQUIRE((long)N * qtiles < (1L << 31) && ptiles <= 65535,
+                 "pole transform: grid too large");
+    hipLaunchKernelGGL(transpose_poles_kernel, dim3((unsigned)(N * qtiles), (unsigned)ptiles),
+                       dim3(256), 0, st, L, N, Q, Qp, p0, np, (int)qtiles, T);
+    AGF2_CHECK_LAUNCH();
+    return;
+  }
   Gemm g;
   g.M = np; g.N = Q; g.K = N; g.batch = N;
   g.A = u + p0; g.sAm = 1; g.sAk = npole;              // A(p, r) = u[r][p0+p]
@@ -875,9 +962,18 @@ void pole_transform_f64(int N, int Q, int Qp, const double* L, const double* u, 
 }
 
 // Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q]
+// u = nullptr: identity coefficients, Lov[i][a][Q] = Lxv[a][i][Q].
 void lov_transform_f64(int N, int Q, int Qp, const double* u, int npole, int o, int v,
                        const double* Lxv, double* Lov, hipStream_t st) {
   if (o == 0 || v == 0) return;
+  if (!u) {
+    const long tot = (long)o * v * Qp;
+    hipLaunchKernelGGL(select_rows_kernel,
+                       dim3((unsigned)std::min<long>((tot + 255) / 256, 16384)), dim3(256), 0,
+                       st, Lxv, N, o, v, Qp, Lov);
+    AGF2_CHECK_LAUNCH();
+    return;
+  }
   Gemm g;
   g.M = o; g.N = Q; g.K = N; g.batch = v;
   g.A = u; g.sAm = 1; g.sAk = npole;
@@ -895,12 +991,13 @@ void build_moments_f64_n(Handle& h, int N, int Q, const double* L, int npole, in
   double* Lxv = h.ws_moments[1].as<double>((long)v * N * Qp);
   double* Lov = h.ws_moments[2].as<double>((long)o * v * Qp);
   {
+    const double* ut = poles_are_identity(h, N, npole, u) ? nullptr : u;
     ProfScope ps(h, "moments.transform",
-                 2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
+                 ut ? 2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v : 0.0,
                  8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
-    pole_transform_f64(N, Q, Qp, L, u, npole, 0, o, Lxo, h.stream);
-    pole_transform_f64(N, Q, Qp, L, u, npole, o, v, Lxv, h.stream);
-    lov_transform_f64(N, Q, Qp, u, npole, o, v, Lxv, Lov, h.stream);
+    pole_transform_f64(N, Q, Qp, L, ut, npole, 0, o, Lxo, h.stream);
+    pole_transform_f64(N, Q, Qp, L, ut, npole, o, v, Lxv, h.stream);
+    lov_transform_f64(N, Q, Qp, ut, npole, o, v, Lxv, Lov, h.stream);
   }
   // lesser: pairs (i, j) occupied, inner a virtual; S[j][a][Q] = Lov[j][a][Q]
   moments_part_f64(h, N, Q, Qp, Lxo, (long)N * Qp, Qp, Lov, (long)v * Qp, Qp,

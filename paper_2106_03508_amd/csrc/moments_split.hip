@@ -1115,8 +1115,9 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
     AGF2_HIP(hipStreamSynchronize(st));
   }
   {
+    const double* ut = poles_are_identity(h, N, npole, u) ? nullptr : u;
     ProfScope ps(h, "moments.transform",
-                 2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v,
+                 ut ? 2.0 * Q * (double)N * N * npole + 2.0 * Q * (double)N * o * v : 0.0,
                  8.0 * ((double)Q * N * N + (double)npole * N * Q + (double)o * v * Q));
     // float64 staging in chunks of poles (<= ~4 GiB each), a multiple of 64
     // poles where possible (whole GEMM tiles)
@@ -1128,7 +1129,7 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
     double* Tov = T + (long)pc * per_pole;
     for (int p0 = 0; p0 < o; p0 += pc) {
       const int np = std::min(pc, o - p0);
-      pole_transform_f64(N, Q, Qp, L, u, npole, p0, np, T, st);
+      pole_transform_f64(N, Q, Qp, L, ut, npole, p0, np, T, st);
       // rows (p, x); one exponent per pole p
       if (F16) row_stats(T, per_pole, Qp, np, N, Q, 1, 0, eRo + p0, nrm + 0, st);
       split_rows<F16>(T, per_pole, Qp, np, N, perm, Rxo_h + (long)p0 * N * KS,
@@ -1137,13 +1138,13 @@ static void build_split(Handle& h, int N, int Q, const double* L, int npole, int
     }
     for (int a0 = 0; a0 < v; a0 += pc) {
       const int na = std::min(pc, v - a0);
-      pole_transform_f64(N, Q, Qp, L, u, npole, o + a0, na, T, st);
+      pole_transform_f64(N, Q, Qp, L, ut, npole, o + a0, na, T, st);
       if (F16) row_stats(T, per_pole, Qp, na, N, Q, 1, 0, eRv + a0, nrm + 1, st);
       split_rows<F16>(T, per_pole, Qp, na, N, perm, Rxv_h + (long)a0 * N * KS,
                       Rxv_l + (long)a0 * N * KS, N, 1, (long)v * N * KS, Qs,
                       F16 ? eRv + a0 : nullptr, 1, 0, st);
       // Lov[i][a][Q] = sum_x u[x][i] Lxv[a][x][Q] for this chunk of a
-      lov_transform_f64(N, Q, Qp, u, npole, o, na, T, Tov, st);
+      lov_transform_f64(N, Q, Qp, ut, npole, o, na, T, Tov, st);
       // rows (i, a); one exponent per row, stored at i * v + a
       if (F16) row_stats(Tov, (long)na * Qp, Qp, o, na, Q, v, 1, eOV + a0, nrm + 2, st);
       split_rows<F16>(Tov, (long)na * Qp, Qp, o, na, perm, Rov_h + (long)a0 * KS,

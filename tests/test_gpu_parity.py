@@ -81,6 +81,33 @@ def test_moments_deterministic(h):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "split_fp16", "split_bf16"])
+@pytest.mark.parametrize("nmo,naux,nocc", [(70, 90, 13), (24, 80, 5), (33, 40, 32)])
+def test_mean_field_poles_relayout_is_the_product(h, monkeypatch, prec, nmo, naux, nocc):
+    """Mean-field poles (u = I, one pole per orbital): the library relays L out
+    instead of multiplying by u. The moments equal, bit for bit, those of the
+    transform run as a product with u (AGF2_NO_IDENTITY_TRANSFORM=1)."""
+    L = syn.df_tensor(7, nmo, naux, nocc)
+    e = syn.orbital_energies(7, nmo, nocc)
+    u = np.eye(nmo)
+    fast = gpu_moments(h, L, e, u, nocc, prec)
+    monkeypatch.setenv("AGF2_NO_IDENTITY_TRANSFORM", "1")
+    prod = gpu_moments(h, L, e, u, nocc, prec)
+    for a, b in zip(fast, prod):
+        assert np.array_equal(a, b)
+    if prec == "fp64":
+        ref = O.se_moments(L, e, u, nocc)
+        assert max(rel(g, r) for g, r in zip(fast, ref)) < MOMENT_TOL
+        # a unit matrix with one off-diagonal entry is not the identity: the
+        # product path runs, and the moments follow the changed coefficients
+        monkeypatch.delenv("AGF2_NO_IDENTITY_TRANSFORM")
+        u2 = u.copy()
+        u2[1, 0] = 1e-3
+        got = gpu_moments(h, L, e, u2, nocc, prec)
+        ref2 = O.se_moments(L, e, u2, nocc)
+        assert max(rel(g, r) for g, r in zip(got, ref2)) < MOMENT_TOL
+
+
 @pytest.mark.parametrize("alpha", [1.0, -1.0])
 def test_fock_build(h, alpha):
     from paper_2106_03508_amd import agf2
