@@ -112,6 +112,11 @@ agf2_status agf2_synchronize(agf2_handle_t handle);
  *   u_pole     device, [nphys][npole] physical amplitudes.
  *   m0_occ, m1_occ, m0_vir, m1_vir   device, [nphys][nphys] outputs,
  *              exactly symmetric.
+ * Mean-field poles (npole = nphys and u_pole exactly the identity, the first
+ * iteration from the mean-field reference) are detected on the device with
+ * one host synchronisation; the pole-basis transform is then a relayout of
+ * Lpq, with the same results bit for bit as the product with u_pole.
+ * Setting AGF2_NO_IDENTITY_TRANSFORM=1 in the environment skips the check.
  * Errors: AGF2_ERR_ARG for bad sizes or NULL pointers, AGF2_ERR_NOMEM when
  * the workspace cannot grow, AGF2_ERR_HIP for a failed launch.
  */
